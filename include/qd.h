@@ -1,0 +1,179 @@
+/*
+ * qd.h - C ABI of libqd, a GPU (gfx950) simulator for mixed-radix qudit
+ * statevectors by block simulation (arXiv 2410.17876, "Fast classical simulation
+ * of qubit-qudit hybrid systems").
+ *
+ * Problem statement (paper Sec. 2): a register of n qudits q_0..q_{n-1} with
+ * dimensions d_0..d_{n-1} (each 2..7 here), q_0 least significant. The state is
+ * the vector of D = prod d_i complex amplitudes; amplitude j belongs to basis
+ * state |j> with j = sum_i x_i s_i, s_i = prod_{t<i} d_t (the block size of
+ * qudit i, Sec. 2.3). A gate applies an M x M unitary U to the target qudits of
+ * every class of amplitudes that differ only in the target digits (Sec. 2.3,
+ * Table 2), optionally only where control qudits hold given values (Sec. 2.4),
+ * without forming a Kronecker product or the D x D operator.
+ *
+ * Conventions shared by every call:
+ *   - Amplitudes are interleaved (re, im). A state holds them on the GPU in
+ *     complex64 (QD_C64, 8 bytes per amplitude) or complex128 (QD_C128, 16 bytes).
+ *     Host-side amplitude buffers are always FP64 interleaved.
+ *   - Gate matrices are M x M complex FP64, row-major U[out][in], interleaved.
+ *     Column a is the image of local basis state |a> (Sec. 2.3), so every class
+ *     x becomes U x. For targets t_0..t_{k-1} the local index is
+ *     a = sum_l a_l prod_{l'<l} d_{t_l'}: the FIRST listed target is the least
+ *     significant local digit. U is rounded once to the state's precision.
+ *   - Every call returns QD_OK (0) or a negative qd_status. No exception or
+ *     abort crosses the ABI. qd_last_error() returns a thread-local message for
+ *     the last failing call of the calling thread.
+ *   - Arguments are validated on the host before any device work, so invalid
+ *     input never reaches a kernel.
+ *   - The caller owns every array it passes; the library copies what it keeps
+ *     before returning, so inputs may be freed or reused right away.
+ *   - Calls that enqueue device work (apply, reset) are asynchronous on the
+ *     state's stream; a device fault is reported by the next synchronizing call
+ *     (qd_norm, qd_probabilities, get/set_amplitudes, qd_synchronize).
+ *   - One state must not be used from two threads at once. Different states on
+ *     different streams are independent.
+ */
+#ifndef QD_H
+#define QD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qd_state qd_state;
+
+enum qd_precision { QD_C64 = 1, QD_C128 = 2 };
+
+enum qd_status {
+    QD_OK = 0,
+    QD_ERR_INVALID_ARGUMENT = -1, /* bad dims, targets, controls, values, sizes or null pointers */
+    QD_ERR_DIM_OVERFLOW = -2,     /* D = prod d_i does not fit a signed 64-bit index */
+    QD_ERR_OUT_OF_MEMORY = -3,    /* a device or pinned host allocation failed */
+    QD_ERR_DEVICE = -4,           /* a HIP runtime call or kernel launch failed */
+    QD_ERR_NOT_SUPPORTED = -5,    /* valid but outside this library's limits (see below) */
+    QD_ERR_BUFFER_TOO_SMALL = -6  /* an external buffer or output length is too small */
+};
+
+enum qd_location { QD_DEVICE = 0, QD_HOST = 1 };
+
+/* Limits. Dims are 2..7. D must stay below 2^63: the paper's largest registers
+ * (62 qubits, 39 qutrits, 31 ququads, 27 ququints, Sec. 3) are exactly the
+ * largest with d^n < 2^63. A gate has 1..3 targets (M <= 343) and at most
+ * QD_MAX_CONTROLS controls. */
+#define QD_MIN_DIM 2
+#define QD_MAX_DIM 7
+#define QD_MAX_QUDITS 62
+#define QD_MAX_TARGETS 3
+#define QD_MAX_M 343
+#define QD_MAX_CONTROLS 24
+
+/* ---- host-only calls (no device needed) ---------------------------------- */
+
+/* D = prod dims[i] for a register of n qudits (Sec. 2). Returns
+ * QD_ERR_INVALID_ARGUMENT for n < 1, n > QD_MAX_QUDITS, a null pointer or a dim
+ * outside 2..7; QD_ERR_DIM_OVERFLOW when D >= 2^63 (Sec. 3 size limit). */
+int qd_dim(const int32_t* dims, int32_t n, uint64_t* D);
+
+/* Validate a gate against a register (Sec. 2.3, 2.4): 1 <= k <= 3 distinct
+ * targets in range; 0 <= m <= QD_MAX_CONTROLS distinct controls in range and
+ * disjoint from the targets; values[l] in [0, d_{controls[l]}). k > 3 or
+ * M > 343 give QD_ERR_NOT_SUPPORTED. controls/values may be null when m == 0. */
+int qd_check_gate(const int32_t* dims, int32_t n, const int32_t* targets, int32_t k,
+                  const int32_t* controls, const int32_t* values, int32_t m);
+
+/* What qd_apply_gate would do for this gate, without doing it. */
+typedef struct {
+    char kernel[64];          /* name of the kernel family that would run */
+    int32_t category;         /* 0 dense (superposition, Sec. 2.3), 1 permutation/monomial
+                                 (Sec. 2.2), 2 diagonal (phase, Sec. 2.1), 3 identity */
+    int32_t M;                /* class size prod d_t over the targets */
+    uint64_t classes;         /* classes the gate visits: D / (M * prod d_c) */
+    uint64_t updated;         /* amplitudes read and written (identity rows/columns skipped) */
+    uint64_t bytes;           /* algorithmic HBM bytes: 2 * updated * bytes per amplitude */
+    uint64_t flops;           /* algorithmic real flops: 8 * classes * M * M for dense,
+                                 8 per scaled amplitude for diagonal/monomial */
+} qd_gate_info;
+
+int qd_gate_info_for(const int32_t* dims, int32_t n, int32_t precision, const int32_t* targets,
+                     int32_t k, const int32_t* controls, const int32_t* values, int32_t m,
+                     const double* U, qd_gate_info* info);
+
+/* Class bases the device decoder produces for classes [first, first + count) of a
+ * gate, in class order (for host-side checks of the decoder). base = address of
+ * local index 0 of the class. */
+int qd_class_bases(const int32_t* dims, int32_t n, const int32_t* targets, int32_t k,
+                   const int32_t* controls, const int32_t* values, int32_t m, uint64_t first,
+                   uint64_t count, uint64_t* bases);
+
+/* ---- states ---------------------------------------------------------------- */
+
+/* Allocate a state of the given dims and precision on the current HIP device,
+ * initialised to |0...0> (Sec. 2.5 starts from |00>). The state owns its buffer
+ * and uses the null stream until qd_state_set_stream. *out receives the handle. */
+int qd_state_create(const int32_t* dims, int32_t n, int32_t precision, qd_state** out);
+
+/* Wrap caller-owned device memory (e.g. a torch tensor) of `bytes` bytes at
+ * device_ptr as a state. Contents are left as they are. The memory must outlive
+ * the state; QD_ERR_BUFFER_TOO_SMALL if bytes < D * bytes per amplitude. */
+int qd_state_create_external(const int32_t* dims, int32_t n, int32_t precision, void* device_ptr,
+                             uint64_t bytes, qd_state** out);
+
+/* Free the state (and its buffer if owned). Waits for its pending work. */
+int qd_state_destroy(qd_state* s);
+
+/* Run this state's work on hip_stream (a hipStream_t; null = default stream).
+ * Work already queued on the previous stream is waited for first. */
+int qd_state_set_stream(qd_state* s, void* hip_stream);
+
+/* Set the state to basis state |j> (0 <= j < D). Asynchronous. */
+int qd_state_reset(qd_state* s, uint64_t j);
+
+/* Copy count FP64 interleaved amplitudes from host memory into the state at
+ * amplitude offset `offset` (rounded to FP32 for QD_C64). Synchronous. */
+int qd_state_set_amplitudes(qd_state* s, const double* host, uint64_t offset, uint64_t count);
+
+/* Copy count amplitudes starting at `offset` to host memory as FP64 interleaved
+ * (exactly widened for QD_C64). Synchronous. */
+int qd_state_get_amplitudes(const qd_state* s, double* host, uint64_t offset, uint64_t count);
+
+/* Dimension, precision and device pointer of the state's amplitude buffer. */
+int qd_state_info(const qd_state* s, uint64_t* D, int32_t* precision, void** device_ptr);
+
+/* ---- the hot path ------------------------------------------------------------ */
+
+/* Apply U to targets[0..k-1], controlled on controls[l] holding values[l]
+ * (Sec. 2.1-2.4), in place and asynchronously on the state's stream. Phase
+ * (diagonal) and permutation (monomial) matrices are detected from their exact
+ * zero pattern and take kernels that move or scale only the amplitudes they
+ * change; all others take the dense class sweep. Only classes that satisfy the
+ * controls are visited. Validation as qd_check_gate. */
+int qd_apply_gate(qd_state* s, const int32_t* targets, int32_t k, const int32_t* controls,
+                  const int32_t* values, int32_t m, const double* U);
+
+/* ||psi||_2 = sqrt(sum_j |a_j|^2), summed in FP64 on the device in a fixed
+ * order (the same result for the same state, run after run). Synchronous. */
+int qd_norm(const qd_state* s, double* out);
+
+/* p_j = |a_j|^2 in FP64 for all j (Sec. 2: the squared amplitude of |j>).
+ * out has len >= D doubles, on the device (location QD_DEVICE, written
+ * asynchronously on the state's stream) or on the host (QD_HOST, synchronous).
+ * QD_ERR_BUFFER_TOO_SMALL if len < D. */
+int qd_probabilities(const qd_state* s, double* out, uint64_t len, int32_t location);
+
+/* Wait for the state's queued work; reports asynchronous device errors. */
+int qd_synchronize(const qd_state* s);
+
+/* ---- misc -------------------------------------------------------------------- */
+
+const char* qd_last_error(void);
+const char* qd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QD_H */

@@ -1,0 +1,241 @@
+"""ctypes binding of libqd (include/qd.h): argument marshalling only.
+
+Every step of the simulation runs in the library's HIP kernels. torch supplies
+device memory (the amplitude buffer is a torch tensor wrapped through
+qd_state_create_external) and the stream (torch's current stream), nothing else.
+There is no fallback: if libqd.so is missing or cannot be loaded, importing
+this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqd.so")
+
+QD_C64, QD_C128 = 1, 2
+QD_DEVICE, QD_HOST = 0, 1
+STATUS = {0: "QD_OK", -1: "QD_ERR_INVALID_ARGUMENT", -2: "QD_ERR_DIM_OVERFLOW", -3: "QD_ERR_OUT_OF_MEMORY",
+          -4: "QD_ERR_DEVICE", -5: "QD_ERR_NOT_SUPPORTED", -6: "QD_ERR_BUFFER_TOO_SMALL"}
+PRECISIONS = {"c64": QD_C64, "c128": QD_C128, QD_C64: QD_C64, QD_C128: QD_C128}
+
+
+class QDError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class GateInfo(C.Structure):
+    _fields_ = [("kernel", C.c_char * 64), ("category", C.c_int32), ("M", C.c_int32), ("classes", C.c_uint64),
+                ("updated", C.c_uint64), ("bytes", C.c_uint64), ("flops", C.c_uint64)]
+
+
+def _load() -> C.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_2410_17876_amd/build.py (or __graft_entry__.build())")
+    L = C.CDLL(LIB_PATH)
+    i32p = C.POINTER(C.c_int32)
+    f64p = C.POINTER(C.c_double)
+    u64p = C.POINTER(C.c_uint64)
+    vp = C.c_void_p
+    sig = {
+        "qd_dim": [i32p, C.c_int32, u64p],
+        "qd_check_gate": [i32p, C.c_int32, i32p, C.c_int32, i32p, i32p, C.c_int32],
+        "qd_gate_info_for": [i32p, C.c_int32, C.c_int32, i32p, C.c_int32, i32p, i32p, C.c_int32, f64p,
+                             C.POINTER(GateInfo)],
+        "qd_class_bases": [i32p, C.c_int32, i32p, C.c_int32, i32p, i32p, C.c_int32, C.c_uint64, C.c_uint64, u64p],
+        "qd_state_create": [i32p, C.c_int32, C.c_int32, C.POINTER(vp)],
+        "qd_state_create_external": [i32p, C.c_int32, C.c_int32, vp, C.c_uint64, C.POINTER(vp)],
+        "qd_state_destroy": [vp],
+        "qd_state_set_stream": [vp, vp],
+        "qd_state_reset": [vp, C.c_uint64],
+        "qd_state_set_amplitudes": [vp, f64p, C.c_uint64, C.c_uint64],
+        "qd_state_get_amplitudes": [vp, f64p, C.c_uint64, C.c_uint64],
+        "qd_state_info": [vp, u64p, i32p, C.POINTER(vp)],
+        "qd_apply_gate": [vp, i32p, C.c_int32, i32p, i32p, C.c_int32, f64p],
+        "qd_norm": [vp, f64p],
+        "qd_probabilities": [vp, f64p, C.c_uint64, C.c_int32],
+        "qd_synchronize": [vp],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    L.qd_last_error.argtypes = []
+    L.qd_last_error.restype = C.c_char_p
+    L.qd_version.argtypes = []
+    L.qd_version.restype = C.c_char_p
+    return L
+
+
+lib = _load()
+
+
+def check(rc: int) -> int:
+    if rc != 0:
+        raise QDError(rc, lib.qd_last_error().decode(errors="replace"))
+    return rc
+
+
+def _i32(x: Sequence[int]):
+    a = np.ascontiguousarray(np.asarray(list(x) or [0], dtype=np.int32))
+    return a, a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _u(U) -> tuple:
+    a = np.ascontiguousarray(np.asarray(U, dtype=np.complex128))
+    if a.ndim != 2 or a.shape[0] != a.shape[1]:
+        raise ValueError("U must be a square matrix")
+    return a, a.view(np.float64).ctypes.data_as(C.POINTER(C.c_double))
+
+
+def dim(dims: Sequence[int]) -> int:
+    d, dp = _i32(dims)
+    out = C.c_uint64()
+    check(lib.qd_dim(dp, len(dims), C.byref(out)))
+    return out.value
+
+
+def check_gate(dims, targets, controls=(), values=()) -> None:
+    d, dp = _i32(dims)
+    t, tp = _i32(targets)
+    c, cp = _i32(controls)
+    v, vp_ = _i32(values)
+    check(lib.qd_check_gate(dp, len(dims), tp, len(targets), cp, vp_, len(controls)))
+
+
+def gate_info(dims, targets, U, controls=(), values=(), precision="c128") -> dict:
+    d, dp = _i32(dims)
+    t, tp = _i32(targets)
+    c, cp = _i32(controls)
+    v, vp_ = _i32(values)
+    u, up = _u(U)
+    info = GateInfo()
+    check(lib.qd_gate_info_for(dp, len(dims), PRECISIONS[precision], tp, len(targets), cp, vp_, len(controls), up,
+                               C.byref(info)))
+    return {"kernel": info.kernel.decode(), "category": info.category, "M": info.M, "classes": info.classes,
+            "updated": info.updated, "bytes": info.bytes, "flops": info.flops}
+
+
+def class_bases(dims, targets, controls=(), values=(), first=0, count=None) -> np.ndarray:
+    d, dp = _i32(dims)
+    t, tp = _i32(targets)
+    c, cp = _i32(controls)
+    v, vp_ = _i32(values)
+    if count is None:
+        M = int(np.prod([dims[x] for x in targets]))
+        cpd = int(np.prod([dims[x] for x in controls])) if controls else 1
+        count = dim(dims) // (M * cpd) - first
+    out = np.empty(max(1, count), dtype=np.uint64)
+    check(lib.qd_class_bases(dp, len(dims), tp, len(targets), cp, vp_, len(controls), first, count,
+                             out.ctypes.data_as(C.POINTER(C.c_uint64))))
+    return out[:count]
+
+
+class State:
+    """A statevector resident on the GPU.
+
+    The amplitude buffer is a torch tensor (``self.buffer``: float64 pairs for
+    c128, float32 pairs for c64); work runs on the torch stream current at
+    creation (or the one given).
+    """
+
+    def __init__(self, dims: Sequence[int], precision="c128", device=None, init: Optional[int] = 0, stream=None):
+        import torch
+
+        self.dims = [int(x) for x in dims]
+        self.precision = PRECISIONS[precision]
+        self.D = dim(self.dims)
+        self.device = torch.device(device if device is not None else "cuda")
+        dt = torch.float64 if self.precision == QD_C128 else torch.float32
+        self.buffer = torch.empty(2 * self.D, dtype=dt, device=self.device)
+        self._h = C.c_void_p()
+        d, dp = _i32(self.dims)
+        with torch.cuda.device(self.device):
+            check(lib.qd_state_create_external(dp, len(self.dims), self.precision, C.c_void_p(self.buffer.data_ptr()),
+                                               self.buffer.numel() * self.buffer.element_size(), C.byref(self._h)))
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            check(lib.qd_state_set_stream(self._h, C.c_void_p(self.stream.cuda_stream)))
+            if init is not None:
+                self.reset(init)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def reset(self, j: int = 0) -> "State":
+        check(lib.qd_state_reset(self._h, int(j)))
+        return self
+
+    def apply(self, targets, U, controls=(), values=()) -> "State":
+        t, tp = _i32(targets)
+        c, cp = _i32(controls)
+        v, vp_ = _i32(values)
+        u, up = _u(U)
+        check(lib.qd_apply_gate(self._h, tp, len(targets), cp, vp_, len(controls), up))
+        return self
+
+    def apply_gate(self, g) -> "State":
+        return self.apply(g.targets, g.U, g.controls, g.values)
+
+    def run(self, gates) -> "State":
+        for g in gates:
+            self.apply_gate(g)
+        return self
+
+    def norm(self) -> float:
+        out = C.c_double()
+        check(lib.qd_norm(self._h, C.byref(out)))
+        return out.value
+
+    def probabilities(self, location: str = "device"):
+        """p_j = |a_j|^2 in FP64: a torch tensor on the device, or a numpy array."""
+        import torch
+
+        if location == "device":
+            out = torch.empty(self.D, dtype=torch.float64, device=self.device)
+            check(lib.qd_probabilities(self._h, C.cast(C.c_void_p(out.data_ptr()), C.POINTER(C.c_double)), self.D,
+                                       QD_DEVICE))
+            return out
+        out = np.empty(self.D, dtype=np.float64)
+        check(lib.qd_probabilities(self._h, out.ctypes.data_as(C.POINTER(C.c_double)), self.D, QD_HOST))
+        return out
+
+    def amplitudes(self, offset: int = 0, count: Optional[int] = None) -> np.ndarray:
+        """Amplitudes [offset, offset+count) as complex128 on the host."""
+        count = self.D - offset if count is None else count
+        out = np.empty(count, dtype=np.complex128)
+        check(lib.qd_state_get_amplitudes(self._h, out.view(np.float64).ctypes.data_as(C.POINTER(C.c_double)),
+                                          offset, count))
+        return out
+
+    def set_amplitudes(self, values, offset: int = 0) -> "State":
+        v = np.ascontiguousarray(np.asarray(values, dtype=np.complex128))
+        check(lib.qd_state_set_amplitudes(self._h, v.view(np.float64).ctypes.data_as(C.POINTER(C.c_double)),
+                                          offset, v.size))
+        return self
+
+    def set_interleaved(self, values: np.ndarray, offset: int = 0) -> "State":
+        """Upload FP64 interleaved (re, im) values starting at amplitude ``offset``."""
+        v = np.ascontiguousarray(values, dtype=np.float64)
+        check(lib.qd_state_set_amplitudes(self._h, v.ctypes.data_as(C.POINTER(C.c_double)), offset, v.size // 2))
+        return self
+
+    def synchronize(self) -> None:
+        check(lib.qd_synchronize(self._h))
+
+    def close(self) -> None:
+        if self._h:
+            lib.qd_state_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

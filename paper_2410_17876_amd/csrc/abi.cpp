@@ -1,0 +1,423 @@
+// abi.cpp - the extern "C" entry points declared in include/qd.h.
+//
+// Everything here is argument checking, state bookkeeping and marshalling; all
+// work on amplitudes runs in the kernels of sweep.hip and reduce.hip.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/qd.h"
+#include "kernels.h"
+#include "plan.h"
+#include "planner.h"
+
+using namespace qd;
+
+namespace {
+
+thread_local std::string g_err;
+
+int set_err(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+int hip_err(hipError_t e, const char* what) {
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(e));
+    return set_err(QD_ERR_DEVICE, buf);
+}
+
+#define QD_HIP(call, what)                        \
+    do {                                          \
+        hipError_t e_ = (call);                   \
+        if (e_ != hipSuccess) return hip_err(e_, what); \
+    } while (0)
+
+// Device-side copies of per-gate data that does not fit the kernel arguments
+// (large gate matrices, member offsets). A ring of slots in device memory is
+// filled from pinned host slots by copies on the state's stream, so a slot is
+// only overwritten after every kernel that read it (stream order); the host
+// slot is reused only after its copy has finished (event).
+struct GateRing {
+    static constexpr size_t kSlot = 2u << 20;  // > 343^2 * 16 + 343 * 8
+    static constexpr int kSlots = 4;
+    unsigned char* host = nullptr;
+    unsigned char* dev = nullptr;
+    hipEvent_t ev[kSlots] = {};
+    bool pending[kSlots] = {};
+    int next = 0;
+
+    int ensure() {
+        if (dev) return QD_OK;
+        if (hipHostMalloc(reinterpret_cast<void**>(&host), kSlot * kSlots, hipHostMallocDefault) != hipSuccess) {
+            host = nullptr;
+            return set_err(QD_ERR_OUT_OF_MEMORY, "pinned gate staging allocation failed");
+        }
+        if (hipMalloc(reinterpret_cast<void**>(&dev), kSlot * kSlots) != hipSuccess) {
+            (void)hipHostFree(host);
+            host = nullptr;
+            dev = nullptr;
+            return set_err(QD_ERR_OUT_OF_MEMORY, "device gate ring allocation failed");
+        }
+        for (int i = 0; i < kSlots; ++i) QD_HIP(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming), "event");
+        return QD_OK;
+    }
+
+    void release() {
+        for (int i = 0; i < kSlots; ++i)
+            if (ev[i]) (void)hipEventDestroy(ev[i]);
+        if (dev) (void)hipFree(dev);
+        if (host) (void)hipHostFree(host);
+        dev = nullptr;
+        host = nullptr;
+    }
+};
+
+}  // namespace
+
+struct qd_state {
+    int n = 0;
+    int32_t dims[QD_MAX_QUDITS] = {};
+    uint64_t D = 0;
+    int precision = 0;
+    void* psi = nullptr;
+    bool owned = false;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    GateRing ring;
+    double* red = nullptr;  // kRedBlocks + 1 doubles of reduction scratch
+};
+
+namespace {
+
+int use_device(const qd_state* s) {
+    int cur = -1;
+    QD_HIP(hipGetDevice(&cur), "hipGetDevice");
+    if (cur != s->device) QD_HIP(hipSetDevice(s->device), "hipSetDevice");
+    return QD_OK;
+}
+
+int check_precision(int32_t precision) {
+    if (precision != QD_C64 && precision != QD_C128)
+        return set_err(QD_ERR_INVALID_ARGUMENT, "precision must be QD_C64 (1) or QD_C128 (2)");
+    return QD_OK;
+}
+
+int new_state(const int32_t* dims, int32_t n, int32_t precision, qd_state** out, uint64_t* D) {
+    if (!out) return set_err(QD_ERR_INVALID_ARGUMENT, "out is null");
+    *out = nullptr;
+    std::string err;
+    int rc = check_dims(dims, n, D, &err);
+    if (rc) return set_err(rc, err);
+    rc = check_precision(precision);
+    if (rc) return rc;
+    const uint64_t ab = amp_bytes(precision);
+    if (*D > UINT64_MAX / ab) return set_err(QD_ERR_DIM_OVERFLOW, "state size in bytes overflows");
+    qd_state* s = new qd_state();
+    s->n = n;
+    std::memcpy(s->dims, dims, sizeof(int32_t) * n);
+    s->D = *D;
+    s->precision = precision;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        delete s;
+        return set_err(QD_ERR_DEVICE, "no HIP device available");
+    }
+    s->device = dev;
+    *out = s;
+    return QD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* qd_last_error(void) { return g_err.c_str(); }
+
+const char* qd_version(void) { return "libqd 0.1 (gfx950)"; }
+
+int qd_dim(const int32_t* dims, int32_t n, uint64_t* D) {
+    std::string err;
+    uint64_t d = 0;
+    int rc = check_dims(dims, n, &d, &err);
+    if (rc) return set_err(rc, err);
+    if (!D) return set_err(QD_ERR_INVALID_ARGUMENT, "D is null");
+    *D = d;
+    return QD_OK;
+}
+
+int qd_check_gate(const int32_t* dims, int32_t n, const int32_t* targets, int32_t k, const int32_t* controls,
+                  const int32_t* values, int32_t m) {
+    std::string err;
+    int rc = check_gate(dims, n, targets, k, controls, values, m, &err);
+    return rc ? set_err(rc, err) : QD_OK;
+}
+
+int qd_gate_info_for(const int32_t* dims, int32_t n, int32_t precision, const int32_t* targets, int32_t k,
+                     const int32_t* controls, const int32_t* values, int32_t m, const double* U,
+                     qd_gate_info* info) {
+    int rc = check_precision(precision);
+    if (rc) return rc;
+    if (!info) return set_err(QD_ERR_INVALID_ARGUMENT, "info is null");
+    GatePlan* p = new GatePlan;
+    std::string err;
+    rc = plan_gate(dims, n, targets, k, controls, values, m, U, p, &err);
+    if (rc == QD_OK) plan_info(*p, precision, info);
+    delete p;
+    return rc ? set_err(rc, err) : QD_OK;
+}
+
+int qd_class_bases(const int32_t* dims, int32_t n, const int32_t* targets, int32_t k, const int32_t* controls,
+                   const int32_t* values, int32_t m, uint64_t first, uint64_t count, uint64_t* bases) {
+    std::string err;
+    int rc = check_gate(dims, n, targets, k, controls, values, m, &err);
+    if (rc) return set_err(rc, err);
+    if (count && !bases) return set_err(QD_ERR_INVALID_ARGUMENT, "bases is null");
+    // The plan's U only decides the category; the decode does not depend on it.
+    std::vector<double> eye(2 * kMaxM * kMaxM, 0.0);
+    GatePlan* p = new GatePlan;
+    rc = plan_gate(dims, n, targets, k, controls, values, m, eye.data(), p, &err);
+    if (rc) {
+        delete p;
+        return set_err(rc, err);
+    }
+    if (first > p->n_classes || count > p->n_classes - first) {
+        delete p;
+        return set_err(QD_ERR_INVALID_ARGUMENT, "class range outside 0..classes");
+    }
+    const bool narrow = p->D < (1ull << 31);
+    if (narrow) {
+        const Decode<uint32_t> dec = make_decode<uint32_t>(*p);
+        for (uint64_t i = 0; i < count; ++i) bases[i] = decode_base<uint32_t>(dec, (uint32_t)(first + i));
+    } else {
+        const Decode<uint64_t> dec = make_decode<uint64_t>(*p);
+        for (uint64_t i = 0; i < count; ++i) bases[i] = decode_base<uint64_t>(dec, first + i);
+    }
+    delete p;
+    return QD_OK;
+}
+
+int qd_state_create(const int32_t* dims, int32_t n, int32_t precision, qd_state** out) {
+    uint64_t D = 0;
+    int rc = new_state(dims, n, precision, out, &D);
+    if (rc) return rc;
+    qd_state* s = *out;
+    const size_t bytes = (size_t)D * amp_bytes(precision);
+    if (hipMalloc(&s->psi, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        delete s;
+        *out = nullptr;
+        return set_err(QD_ERR_OUT_OF_MEMORY, "device allocation of the state failed");
+    }
+    s->owned = true;
+    hipError_t e = launch_basis(s->psi, precision, D, 0, s->stream);
+    if (e != hipSuccess) {
+        (void)hipFree(s->psi);
+        delete s;
+        *out = nullptr;
+        return hip_err(e, "initial state");
+    }
+    return QD_OK;
+}
+
+int qd_state_create_external(const int32_t* dims, int32_t n, int32_t precision, void* device_ptr, uint64_t bytes,
+                             qd_state** out) {
+    if (!device_ptr) return set_err(QD_ERR_INVALID_ARGUMENT, "device_ptr is null");
+    uint64_t D = 0;
+    int rc = new_state(dims, n, precision, out, &D);
+    if (rc) return rc;
+    if (bytes / amp_bytes(precision) < D) {
+        delete *out;
+        *out = nullptr;
+        return set_err(QD_ERR_BUFFER_TOO_SMALL, "external buffer smaller than D amplitudes");
+    }
+    (*out)->psi = device_ptr;
+    (*out)->owned = false;
+    return QD_OK;
+}
+
+int qd_state_destroy(qd_state* s) {
+    if (!s) return QD_OK;
+    use_device(s);
+    (void)hipStreamSynchronize(s->stream);
+    s->ring.release();
+    if (s->red) (void)hipFree(s->red);
+    if (s->owned && s->psi) (void)hipFree(s->psi);
+    delete s;
+    return QD_OK;
+}
+
+int qd_state_set_stream(qd_state* s, void* hip_stream) {
+    if (!s) return set_err(QD_ERR_INVALID_ARGUMENT, "state is null");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    if (st == s->stream) return QD_OK;
+    int rc = use_device(s);
+    if (rc) return rc;
+    QD_HIP(hipStreamSynchronize(s->stream), "synchronizing the previous stream");
+    s->stream = st;
+    return QD_OK;
+}
+
+int qd_state_reset(qd_state* s, uint64_t j) {
+    if (!s) return set_err(QD_ERR_INVALID_ARGUMENT, "state is null");
+    if (j >= s->D) return set_err(QD_ERR_INVALID_ARGUMENT, "basis index outside 0..D-1");
+    int rc = use_device(s);
+    if (rc) return rc;
+    QD_HIP(launch_basis(s->psi, s->precision, s->D, j, s->stream), "reset");
+    return QD_OK;
+}
+
+int qd_state_info(const qd_state* s, uint64_t* D, int32_t* precision, void** device_ptr) {
+    if (!s) return set_err(QD_ERR_INVALID_ARGUMENT, "state is null");
+    if (D) *D = s->D;
+    if (precision) *precision = s->precision;
+    if (device_ptr) *device_ptr = s->psi;
+    return QD_OK;
+}
+
+int qd_state_set_amplitudes(qd_state* s, const double* host, uint64_t offset, uint64_t count) {
+    if (!s) return set_err(QD_ERR_INVALID_ARGUMENT, "state is null");
+    if (count && !host) return set_err(QD_ERR_INVALID_ARGUMENT, "host is null");
+    if (offset > s->D || count > s->D - offset) return set_err(QD_ERR_INVALID_ARGUMENT, "range outside the state");
+    int rc = use_device(s);
+    if (rc) return rc;
+    if (s->precision == QD_C128) {
+        QD_HIP(hipMemcpyAsync(static_cast<double*>(s->psi) + 2 * offset, host, count * 16, hipMemcpyHostToDevice,
+                              s->stream),
+               "copy to device");
+        QD_HIP(hipStreamSynchronize(s->stream), "copy to device");
+        return QD_OK;
+    }
+    const uint64_t chunk = 1ull << 22;
+    std::vector<float> tmp(2 * std::min<uint64_t>(chunk, count ? count : 1));
+    for (uint64_t done = 0; done < count; done += chunk) {
+        const uint64_t c = std::min<uint64_t>(chunk, count - done);
+        for (uint64_t i = 0; i < 2 * c; ++i) tmp[i] = static_cast<float>(host[2 * done + i]);
+        QD_HIP(hipMemcpyAsync(static_cast<float*>(s->psi) + 2 * (offset + done), tmp.data(), c * 8,
+                              hipMemcpyHostToDevice, s->stream),
+               "copy to device");
+        QD_HIP(hipStreamSynchronize(s->stream), "copy to device");
+    }
+    return QD_OK;
+}
+
+int qd_state_get_amplitudes(const qd_state* s, double* host, uint64_t offset, uint64_t count) {
+    if (!s) return set_err(QD_ERR_INVALID_ARGUMENT, "state is null");
+    if (count && !host) return set_err(QD_ERR_INVALID_ARGUMENT, "host is null");
+    if (offset > s->D || count > s->D - offset) return set_err(QD_ERR_INVALID_ARGUMENT, "range outside the state");
+    int rc = use_device(s);
+    if (rc) return rc;
+    if (s->precision == QD_C128) {
+        QD_HIP(hipMemcpyAsync(host, static_cast<const double*>(s->psi) + 2 * offset, count * 16,
+                              hipMemcpyDeviceToHost, s->stream),
+               "copy to host");
+        QD_HIP(hipStreamSynchronize(s->stream), "copy to host");
+        return QD_OK;
+    }
+    const uint64_t chunk = 1ull << 22;
+    std::vector<float> tmp(2 * std::min<uint64_t>(chunk, count ? count : 1));
+    for (uint64_t done = 0; done < count; done += chunk) {
+        const uint64_t c = std::min<uint64_t>(chunk, count - done);
+        QD_HIP(hipMemcpyAsync(tmp.data(), static_cast<const float*>(s->psi) + 2 * (offset + done), c * 8,
+                              hipMemcpyDeviceToHost, s->stream),
+               "copy to host");
+        QD_HIP(hipStreamSynchronize(s->stream), "copy to host");
+        for (uint64_t i = 0; i < 2 * c; ++i) host[2 * done + i] = static_cast<double>(tmp[i]);
+    }
+    return QD_OK;
+}
+
+int qd_apply_gate(qd_state* s, const int32_t* targets, int32_t k, const int32_t* controls, const int32_t* values,
+                  int32_t m, const double* U) {
+    if (!s) return set_err(QD_ERR_INVALID_ARGUMENT, "state is null");
+    GatePlan p;
+    std::string err;
+    int rc = plan_gate(s->dims, s->n, targets, k, controls, values, m, U, &p, &err);
+    if (rc) return set_err(rc, err);
+    rc = use_device(s);
+    if (rc) return rc;
+    const size_t gbytes = device_gate_bytes(p, s->precision);
+    const void* dgate = nullptr;
+    if (gbytes) {
+        rc = s->ring.ensure();
+        if (rc) return rc;
+        GateRing& r = s->ring;
+        const int slot = r.next;
+        r.next = (r.next + 1) % GateRing::kSlots;
+        if (r.pending[slot]) QD_HIP(hipEventSynchronize(r.ev[slot]), "gate staging");
+        unsigned char* h = r.host + slot * GateRing::kSlot;
+        unsigned char* d = r.dev + slot * GateRing::kSlot;
+        fill_device_gate(p, s->precision, U, h);
+        QD_HIP(hipMemcpyAsync(d, h, gbytes, hipMemcpyHostToDevice, s->stream), "gate upload");
+        QD_HIP(hipEventRecord(r.ev[slot], s->stream), "gate staging");
+        r.pending[slot] = true;
+        dgate = d;
+    }
+    QD_HIP(launch_gate(p, s->precision, s->psi, U, dgate, s->stream), "gate launch");
+    return QD_OK;
+}
+
+int qd_norm(const qd_state* s, double* out) {
+    if (!s || !out) return set_err(QD_ERR_INVALID_ARGUMENT, "state or out is null");
+    int rc = use_device(s);
+    if (rc) return rc;
+    qd_state* ms = const_cast<qd_state*>(s);
+    if (!ms->red) {
+        if (hipMalloc(reinterpret_cast<void**>(&ms->red), (kRedBlocks + 1) * sizeof(double)) != hipSuccess) {
+            ms->red = nullptr;
+            return set_err(QD_ERR_OUT_OF_MEMORY, "reduction scratch allocation failed");
+        }
+    }
+    QD_HIP(launch_sumsq(s->psi, s->precision, s->D, ms->red, s->stream), "norm");
+    double sum = 0.0;
+    QD_HIP(hipMemcpyAsync(&sum, ms->red + kRedBlocks, sizeof(double), hipMemcpyDeviceToHost, s->stream), "norm");
+    QD_HIP(hipStreamSynchronize(s->stream), "norm");
+    *out = std::sqrt(sum);
+    return QD_OK;
+}
+
+int qd_probabilities(const qd_state* s, double* out, uint64_t len, int32_t location) {
+    if (!s || !out) return set_err(QD_ERR_INVALID_ARGUMENT, "state or out is null");
+    if (location != QD_DEVICE && location != QD_HOST)
+        return set_err(QD_ERR_INVALID_ARGUMENT, "location must be QD_DEVICE or QD_HOST");
+    if (len < s->D) return set_err(QD_ERR_BUFFER_TOO_SMALL, "output shorter than D");
+    int rc = use_device(s);
+    if (rc) return rc;
+    if (location == QD_DEVICE) {
+        QD_HIP(launch_probabilities(s->psi, s->precision, 0, s->D, out, s->stream), "probabilities");
+        return QD_OK;
+    }
+    const uint64_t chunk = std::min<uint64_t>(s->D, 1ull << 24);
+    double* tmp = nullptr;
+    if (hipMalloc(reinterpret_cast<void**>(&tmp), chunk * sizeof(double)) != hipSuccess)
+        return set_err(QD_ERR_OUT_OF_MEMORY, "probability staging allocation failed");
+    for (uint64_t done = 0; done < s->D; done += chunk) {
+        const uint64_t c = std::min<uint64_t>(chunk, s->D - done);
+        hipError_t e = launch_probabilities(s->psi, s->precision, done, c, tmp, s->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(out + done, tmp, c * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+        if (e != hipSuccess) {
+            (void)hipFree(tmp);
+            return hip_err(e, "probabilities");
+        }
+    }
+    (void)hipFree(tmp);
+    return QD_OK;
+}
+
+int qd_synchronize(const qd_state* s) {
+    if (!s) return set_err(QD_ERR_INVALID_ARGUMENT, "state is null");
+    int rc = use_device(s);
+    if (rc) return rc;
+    QD_HIP(hipStreamSynchronize(s->stream), "synchronize");
+    QD_HIP(hipGetLastError(), "asynchronous error");
+    return QD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,39 @@
+// kernels.h - host-side launchers of the device kernels (sweep.hip, reduce.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "plan.h"
+
+namespace qd {
+
+enum Precision { kC64 = 1, kC128 = 2 };
+
+inline size_t amp_bytes(int precision) { return precision == kC128 ? 16 : 8; }
+
+// Which kernel family a plan takes.
+enum Family { kFamIdentity = 0, kFamDenseReg = 1, kFamDenseLds = 2, kFamMonomial = 3 };
+int plan_family(const GatePlan& p);
+const char* family_name(int family);
+
+// Bytes of device-side gate data (rounded U, member offsets) a plan needs, 0 if
+// everything travels in the kernel arguments.
+size_t device_gate_bytes(const GatePlan& p, int precision);
+// Fill `dst` (host staging memory, device_gate_bytes long) with that data.
+void fill_device_gate(const GatePlan& p, int precision, const double* U, void* dst);
+
+// Enqueue the gate on `stream`. dgate: device copy of fill_device_gate's output
+// (ignored when device_gate_bytes is 0). Returns hipSuccess or the launch error.
+hipError_t launch_gate(const GatePlan& p, int precision, void* psi, const double* U, const void* dgate,
+                       hipStream_t stream);
+
+// Reductions and fills (reduce.hip).
+constexpr int kRedBlocks = 1024;
+hipError_t launch_sumsq(const void* psi, int precision, uint64_t D, double* scratch /* kRedBlocks+1 */,
+                        hipStream_t stream);  // result in scratch[kRedBlocks]
+hipError_t launch_probabilities(const void* psi, int precision, uint64_t offset, uint64_t count,
+                                double* out, hipStream_t stream);
+hipError_t launch_basis(void* psi, int precision, uint64_t D, uint64_t j, hipStream_t stream);
+
+}  // namespace qd

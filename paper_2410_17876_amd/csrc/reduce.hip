@@ -1,0 +1,112 @@
+// reduce.hip - FP64 reductions and fills over a statevector.
+//
+// The norm is sqrt(sum_j |a_j|^2) (the squared amplitudes are the basis-state
+// probabilities, paper Sec. 2). It is accumulated in FP64 whatever the state's
+// precision, in a fixed order: kRedBlocks workgroups each take a fixed strided
+// share, sum it with Kahan compensation, reduce over the workgroup by a fixed
+// tree, and a single workgroup adds the partials in a fixed tree. The result
+// depends only on the state's contents, never on timing.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace qd {
+
+template <typename T>
+__device__ __forceinline__ double sq(const T& a) {
+    const double x = (double)a.x, y = (double)a.y;
+    return x * x + y * y;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    return sh[0];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void sumsq_partial(const T* __restrict__ psi, uint64_t D,
+                                                     double* __restrict__ partial) {
+    __shared__ double sh[256];
+    double s = 0.0, c = 0.0;
+    const uint64_t stride = (uint64_t)gridDim.x * 256;
+    for (uint64_t j = (uint64_t)blockIdx.x * 256 + threadIdx.x; j < D; j += stride) {
+        const double y = sq(psi[j]) - c;
+        const double t = s + y;
+        c = (t - s) - y;
+        s = t;
+    }
+    const double tot = block_sum(s, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(256) void sumsq_final(double* __restrict__ partial, int nb) {
+    __shared__ double sh[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nb; i += 256) s += partial[i];
+    const double tot = block_sum(s, sh);
+    if (threadIdx.x == 0) partial[nb] = tot;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void probabilities_k(const T* __restrict__ psi, uint64_t offset,
+                                                       uint64_t count, double* __restrict__ out) {
+    const uint64_t stride = (uint64_t)gridDim.x * 256;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < count; i += stride)
+        out[i] = sq(psi[offset + i]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void basis_fill(T* __restrict__ psi, uint64_t D, uint64_t j) {
+    const uint64_t stride = (uint64_t)gridDim.x * 256;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < D; i += stride) {
+        T v;
+        v.x = i == j ? 1 : 0;
+        v.y = 0;
+        psi[i] = v;
+    }
+}
+
+static unsigned grid_for(uint64_t n) {
+    const uint64_t b = (n + 255) / 256;
+    return (unsigned)(b < 8192 ? (b ? b : 1) : 8192);
+}
+
+hipError_t launch_sumsq(const void* psi, int precision, uint64_t D, double* scratch, hipStream_t st) {
+    if (precision == kC128)
+        hipLaunchKernelGGL(sumsq_partial<double2>, dim3(kRedBlocks), dim3(256), 0, st,
+                           static_cast<const double2*>(psi), D, scratch);
+    else
+        hipLaunchKernelGGL(sumsq_partial<float2>, dim3(kRedBlocks), dim3(256), 0, st,
+                           static_cast<const float2*>(psi), D, scratch);
+    hipLaunchKernelGGL(sumsq_final, dim3(1), dim3(256), 0, st, scratch, kRedBlocks);
+    return hipGetLastError();
+}
+
+hipError_t launch_probabilities(const void* psi, int precision, uint64_t offset, uint64_t count, double* out,
+                                hipStream_t st) {
+    if (count == 0) return hipSuccess;
+    if (precision == kC128)
+        hipLaunchKernelGGL(probabilities_k<double2>, dim3(grid_for(count)), dim3(256), 0, st,
+                           static_cast<const double2*>(psi), offset, count, out);
+    else
+        hipLaunchKernelGGL(probabilities_k<float2>, dim3(grid_for(count)), dim3(256), 0, st,
+                           static_cast<const float2*>(psi), offset, count, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_basis(void* psi, int precision, uint64_t D, uint64_t j, hipStream_t st) {
+    if (precision == kC128)
+        hipLaunchKernelGGL(basis_fill<double2>, dim3(grid_for(D)), dim3(256), 0, st, static_cast<double2*>(psi),
+                           D, j);
+    else
+        hipLaunchKernelGGL(basis_fill<float2>, dim3(grid_for(D)), dim3(256), 0, st, static_cast<float2*>(psi), D,
+                           j);
+    return hipGetLastError();
+}
+
+}  // namespace qd

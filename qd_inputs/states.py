@@ -46,6 +46,12 @@ def labelled(start: int, count: int) -> np.ndarray:
     return (j & 0xFFFFF).astype(np.float64) + 1j * (j >> 20).astype(np.float64)
 
 
+def labelled_at(idx) -> np.ndarray:
+    """The index-labelled state's values at arbitrary indices."""
+    j = np.asarray(idx, dtype=np.int64)
+    return (j & 0xFFFFF).astype(np.float64) + 1j * (j >> 20).astype(np.float64)
+
+
 def _threads() -> int:
     return max(1, min(16, os.cpu_count() or 1))
 
@@ -59,6 +65,8 @@ class GaussianState:
         self.chunk = int(chunk)
         self.nchunks = (self.D + self.chunk - 1) // self.chunk
         self._scale: Optional[float] = None
+        self._cache: "dict[int, np.ndarray]" = {}
+        self.cache_chunks = 0  # chunks kept by values(); 0 = none
 
     def _raw(self, c: int) -> np.ndarray:
         n = min(self.chunk, self.D - c * self.chunk)
@@ -93,9 +101,14 @@ class GaussianState:
         ch = flat // self.chunk
         s = self.scale
         for c in np.unique(ch):
+            c = int(c)
             sel = np.nonzero(ch == c)[0]
-            v = self.chunk_values(int(c), s).view(np.complex128)
-            res[sel] = v[flat[sel] - int(c) * self.chunk]
+            v = self._cache.get(c)
+            if v is None:
+                v = self.chunk_values(c, s).view(np.complex128)
+                if len(self._cache) < self.cache_chunks:
+                    self._cache[c] = v
+            res[sel] = v[flat[sel] - c * self.chunk]
         return out
 
     def fill(self, sink: Callable[[int, np.ndarray], None], window: int = 0) -> None:

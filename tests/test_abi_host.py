@@ -1,0 +1,153 @@
+"""The C-ABI library on the host: it loads, exports every declared symbol, and
+its host-side logic (validation, planning, class decoder) is right. No call
+here touches a device."""
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2410_17876_amd as qd
+from qd_inputs import clock, dft, haar, shift
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", fn)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(qd_\w+)\s*\(", src, flags=re.M))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_symbols()
+    assert len(names) >= 17
+    lib = C.CDLL(qd.LIB_PATH)
+    missing = [n for n in sorted(names) if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_dim_limits_match_64bit_index_limits():
+    # The paper's largest registers (Sec. 3): 62 qubits, 39 qutrits, 31 ququads,
+    # 27 ququints, limited by a signed 64-bit basis index.
+    for d, n_max in ((2, 62), (3, 39), (4, 31), (5, 27)):
+        assert qd.dim([d] * n_max) == d ** n_max
+        with pytest.raises(qd.QDError) as e:
+            qd.dim([d] * (n_max + 1))
+        assert e.value.code in (-1, -2)
+    with pytest.raises(qd.QDError) as e:
+        qd.dim([7] * 23)
+    assert e.value.code == -2
+    for bad in ([1], [8], [2, 0], []):
+        with pytest.raises(qd.QDError) as e:
+            qd.dim(bad)
+        assert e.value.code == -1
+
+
+@pytest.mark.parametrize("targets,controls,values,code", [
+    ([0, 0], [], [], -1),          # duplicate target
+    ([3], [], [], -1),             # target out of range
+    ([], [], [], -1),              # no target
+    ([0], [0], [1], -1),           # control equals target
+    ([0], [1, 1], [0, 0], -1),     # duplicate control
+    ([0], [1], [3], -1),           # control value >= d_c
+    ([0], [1], [-1], -1),          # negative control value
+    ([0, 1, 2], [], [], 0),        # three targets: fine
+])
+def test_gate_validation(targets, controls, values, code):
+    dims = [2, 3, 4]
+    if code == 0:
+        qd.check_gate(dims, targets, controls, values)
+    else:
+        with pytest.raises(qd.QDError) as e:
+            qd.check_gate(dims, targets, controls, values)
+        assert e.value.code == code
+
+
+def test_four_targets_not_supported():
+    with pytest.raises(qd.QDError) as e:
+        qd.check_gate([2, 2, 2, 2], [0, 1, 2, 3])
+    assert e.value.code == -5
+
+
+def test_null_pointers_rejected():
+    lib = qd.lib
+    assert lib.qd_dim(None, 3, None) == -1
+    dims = (C.c_int32 * 2)(2, 3)
+    assert lib.qd_check_gate(dims, 2, None, 1, None, None, 0) == -1
+    assert lib.qd_state_reset(None, 0) == -1
+    assert lib.qd_norm(None, None) == -1
+    assert lib.qd_apply_gate(None, None, 1, None, None, 0, None) == -1
+    assert "null" in lib.qd_last_error().decode()
+
+
+def test_gate_categories_from_zero_pattern():
+    rng = np.random.default_rng(0)
+    dims = [2, 3, 5]
+    assert qd.gate_info(dims, [1], dft(3))["category"] == 0
+    assert qd.gate_info(dims, [1], haar(3, rng))["category"] == 0
+    assert qd.gate_info(dims, [2], shift(5, 2))["category"] == 1
+    z = qd.gate_info(dims, [2], clock(5))
+    assert z["category"] == 2 and z["updated"] == 2 * 3 * 4 and z["bytes"] == 2 * 24 * 16
+    assert qd.gate_info(dims, [2], np.eye(5))["category"] == 3
+    cx = qd.gate_info(dims, [0], shift(2), [2], [4], precision="c64")
+    assert cx["category"] == 1 and cx["classes"] == 3 and cx["updated"] == 6 and cx["bytes"] == 2 * 6 * 8
+    h = qd.gate_info(dims, [0, 2], haar(10, rng))
+    assert h["kernel"] == "sweep_dense_reg" and h["flops"] == 8 * 30 * 10
+    assert qd.gate_info([5, 5, 5, 2], [0, 1, 2], haar(125, rng))["kernel"] == "sweep_dense_lds"
+
+
+def _rand_case(rng):
+    while True:
+        n = int(rng.integers(1, 7))
+        dims = [int(x) for x in rng.integers(2, 8, size=n)]
+        if math.prod(dims) <= 50000:
+            break
+    k = int(rng.integers(1, min(3, n) + 1))
+    targets = [int(x) for x in rng.choice(n, k, replace=False)]
+    rest = [q for q in range(n) if q not in targets]
+    m = int(rng.integers(0, len(rest) + 1))
+    controls = [int(x) for x in rng.choice(rest, m, replace=False)] if m else []
+    values = [int(rng.integers(dims[c])) for c in controls]
+    return dims, targets, controls, values
+
+
+def test_decoder_matches_oracle_classes():
+    rng = np.random.default_rng(1)
+    for _ in range(300):
+        dims, targets, controls, values = _rand_case(rng)
+        D = math.prod(dims)
+        bases = qd.class_bases(dims, targets, controls, values).astype(np.int64)
+        members, row = oracle.class_members(dims, targets, controls, values, np.arange(D))
+        want = np.unique(members[row >= 0, 0])
+        assert np.array_equal(bases, want)
+
+
+def test_decoder_64bit_path_against_oracle_samples():
+    # D >= 2^31 takes the 64-bit decoder; the oracle's sampled form needs no state.
+    rng = np.random.default_rng(2)
+    for dims in ([2] * 31 + [3], [7] * 12, [3, 5, 7, 2] * 5):
+        D = math.prod(dims)
+        assert D >= 2**31
+        for _ in range(20):
+            k = int(rng.integers(1, 4))
+            targets = [int(x) for x in rng.choice(len(dims), k, replace=False)]
+            rest = [q for q in range(len(dims)) if q not in targets]
+            controls = [int(x) for x in rng.choice(rest, int(rng.integers(0, 3)), replace=False)]
+            values = [int(rng.integers(dims[c])) for c in controls]
+            n_cls = D // (math.prod(dims[t] for t in targets) * math.prod(dims[c] for c in controls))
+            first = int(rng.integers(0, n_cls - 64))
+            bases = qd.class_bases(dims, targets, controls, values, first, 64).astype(np.int64)
+            members, row = oracle.class_members(dims, targets, controls, values, bases)
+            assert (row == 0).all() and np.array_equal(members[:, 0], bases)
+            assert (np.diff(bases) > 0).all()
+            last = qd.class_bases(dims, targets, controls, values, n_cls - 1, 1).astype(np.int64)
+            m2, r2 = oracle.class_members(dims, targets, controls, values, last)
+            assert r2[0] == 0
