@@ -1,29 +1,39 @@
 #!/usr/bin/env python3
-"""Benchmark of the block-simulation gate sweep on one MI355X.
+"""Benchmark of block-simulation gate application on one MI355X.
 
-Workload: the large mixed-radix register 2^14 x 3^8 x 4^2 (D = 1.72e9
-amplitudes; q_0..q_13 qubits, q_14..q_21 qutrits, q_22..q_23 ququads), a
-normalised complex Gaussian initial state (seed 1001) resident in HBM, and a
-500-gate circuit: w.p. 0.1 a 2-qudit Haar unitary, else the basic mix (1-qudit
-Haar 60%, DFT/X/Z 20%, controlled X 20%). One step = the whole circuit applied
-once, followed by the FP64 norm reduction. The complex128 run is the headline;
-the complex64 run of the same circuit is reported beside it.
+Workload: the mixed-radix register 2^14 x 3^8 x 4^2 (D = 1.72e9 amplitudes;
+q_0..q_13 qubits, q_14..q_21 qutrits, q_22..q_23 ququads), a normalised complex
+Gaussian initial state (seed 1001) resident in HBM, and a 500-gate circuit: w.p.
+0.1 a 2-qudit Haar unitary, else the basic mix (1-qudit Haar 60%, DFT/X/Z 20%,
+controlled X 20%). One step = the whole circuit applied once, then the FP64
+norm. Four runs of the same circuit:
+
+  fused c128   qd_apply_circuit with LDS-staged fusion (the library's default
+               circuit path) -- the headline `value`
+  plain c128   one sweep per gate (qd_apply_gate)
+  fused c64, plain c64
 
 Metric: gate-amplitude updates/s = sum over gates of the amplitudes each gate
-reads and writes (identity rows of U skipped, only classes that satisfy the
-controls) / wall time of the timed steps. Algorithmic bytes = 2 x updates x
-bytes per amplitude.
+changes (identity rows of U skipped; only classes whose controls hold) / wall
+time of the timed steps. It counts per original gate, so fusion raises it
+without moving more bytes.
 
-Roofline: for the kernel instantiation with the largest total time, algorithmic
-bytes of its launches / their summed durations, measured with HIP events around
-every launch on the stream the kernels run on, against 8 TB/s.
+Roofline: for the kernel instantiation with the largest total time, the bytes
+it must move per launch (plain sweep: 2 x changed amplitudes x bytes; fused
+pass: 2 x D x bytes, one read and one write of the whole state) / its average
+launch time, measured with HIP events around every launch on the stream the
+kernels run on, against 8 TB/s. `traffic` is the counter-measured HBM bytes per
+launch (profiles/*traffic*.json, when taken for the current kernel source).
 
-CPU baseline: the FP64 oracle (single thread) on the same state and circuit,
-timed on its first gates until about --cpu-seconds have passed.
+Also reported: the in-place read+rewrite copy ceiling measured on the same
+buffer (qd_copy_ceiling), and the FP64 oracle (one thread) on the first gates
+of the same circuit and state as the CPU baseline.
 """
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import math
 import os
@@ -50,89 +60,148 @@ def kernel_key(info: dict, precision: str) -> str:
     return f"{info['kernel']}<{t},M={info['M']}>"
 
 
-def run_precision(qd, dims, gates, precision, upload, steps, warmup):
+def source_digest() -> str:
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2410_17876_amd", "csrc", "*"))):
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str):
+    """Counter-measured bytes per launch for `kernel`, if taken on the current source."""
+    digest = source_digest()
+    for f in glob.glob(os.path.join(ROOT, "profiles", "*traffic*.json")):
+        try:
+            d = json.load(open(f))
+        except Exception:
+            continue
+        if d.get("kernel") == kernel and d.get("source_digest") == digest:
+            return d.get("bytes_per_launch")
+    return None
+
+
+TILE = {"c128": 0, "c64": 0}
+
+
+def build_units(qd, dims, gates, precision, mode):
+    """The launches of one step: (key, bytes per launch, updates, callable)."""
+    D = math.prod(dims)
+    ab = 16 if precision == "c128" else 8
+    infos = [qd.gate_info(dims, g.targets, g.U, g.controls, g.values, precision) for g in gates]
+    units = []
+    if mode == "plain":
+        for g, info in zip(gates, infos):
+            if info["kernel"] == "identity":
+                continue
+            units.append((kernel_key(info, precision), info["bytes"], info["updated"], ("gate", g)))
+        return units
+    plan = qd.circuit_plan(dims, gates, precision, tile_amps=TILE[precision])
+    live = [i for i, info in enumerate(infos) if info["kernel"] != "identity"]
+    pos = 0
+    for ngates, tile in plan:
+        idx = live[pos:pos + ngates]
+        pos += ngates
+        upd = sum(infos[i]["updated"] for i in idx)
+        if tile:
+            t = "double" if precision == "c128" else "float"
+            units.append((f"fused_tile<{t}>", 2 * D * ab, upd, ("pass", qd.GateList([gates[i] for i in idx]))))
+        else:
+            i = idx[0]
+            units.append((kernel_key(infos[i], precision), infos[i]["bytes"], upd, ("gate", gates[i])))
+    assert pos == len(live)
+    return units
+
+
+def run_mode(qd, st, dims, gates, precision, mode, steps, warmup):
     import torch
 
-    infos = [qd.gate_info(dims, g.targets, g.U, g.controls, g.values, precision) for g in gates]
-    keys = [kernel_key(i, precision) for i in infos]
-    st = qd.State(dims, precision, init=None)
-    t0 = time.time()
-    upload(st)
-    st.synchronize()
-    log(f"{precision}: state of {st.D} amplitudes uploaded in {time.time() - t0:.1f} s")
+    units = build_units(qd, dims, gates, precision, mode)
     stream = st.stream
 
     def step(events=None):
-        for gi, g in enumerate(gates):
+        for u, (_, _, _, (kind, obj)) in enumerate(units):
             if events is not None:
-                events[gi][0].record(stream)
-            st.apply_gate(g)
+                events[u][0].record(stream)
+            if kind == "gate":
+                st.apply_gate(obj)
+            else:
+                st.run_circuit(obj, fuse=True, tile_amps=TILE[precision])
             if events is not None:
-                events[gi][1].record(stream)
+                events[u][1].record(stream)
         return st.norm()
 
     for w in range(warmup):
         nrm = step()
-        log(f"{precision}: warmup step {w} done, norm {nrm:.15f}")
-    evs = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in gates]
+        log(f"{mode} {precision}: warmup step {w} done, norm {nrm:.15f}")
+    evs = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in units]
            for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    norms = []
-    for k in range(steps):
-        norms.append(step(evs[k]))
+    norms = [step(evs[k]) for k in range(steps)]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    log(f"{precision}: {steps} timed steps in {wall:.3f} s, norms {[round(x, 12) for x in norms]}")
+    log(f"{mode} {precision}: {steps} timed steps in {wall:.3f} s ({len(units)} launches per step), "
+        f"norms {[round(x, 12) for x in norms]}")
 
     per = {}
     for k in range(steps):
-        for gi, info in enumerate(infos):
-            ms = evs[k][gi][0].elapsed_time(evs[k][gi][1])
-            e = per.setdefault(keys[gi], {"launches": 0, "ms": 0.0, "bytes": 0})
+        for u, (key, nbytes, _, _) in enumerate(units):
+            e = per.setdefault(key, {"launches": 0, "ms": 0.0, "bytes": 0})
             e["launches"] += 1
-            e["ms"] += ms
-            e["bytes"] += info["bytes"]
-    updates = steps * sum(i["updated"] for i in infos)
-    bytes_total = steps * sum(i["bytes"] for i in infos)
-    kernels = {}
-    for key, e in per.items():
-        if key == "identity":
-            continue
-        kernels[key] = {"launches": e["launches"], "avg_us": round(1e3 * e["ms"] / e["launches"], 2),
-                        "total_ms": round(e["ms"], 3),
-                        "GBps": round(e["bytes"] / (e["ms"] * 1e-3) / 1e9, 1) if e["ms"] > 0 else None}
+            e["ms"] += evs[k][u][0].elapsed_time(evs[k][u][1])
+            e["bytes"] += nbytes
+    updates = steps * sum(u[2] for u in units)
+    kernels = {key: {"launches": e["launches"], "avg_us": round(1e3 * e["ms"] / e["launches"], 2),
+                     "total_ms": round(e["ms"], 3),
+                     "GBps": round(e["bytes"] / (e["ms"] * 1e-3) / 1e9, 1) if e["ms"] > 0 else None}
+               for key, e in per.items()}
     dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
     d = per[dom]
     achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
-    out = {
+    traffic = load_traffic(dom)
+    return {
         "value": updates / wall,
         "ms_per_step": 1e3 * wall / steps,
+        "launches_per_step": len(units),
         "updates_per_step": updates // steps,
-        "algorithmic_GBps": bytes_total / wall / 1e9,
         "norm_last_step": norms[-1],
-        "dominant": dom,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": None,
-                     "kernel": dom, "avg_us": kernels[dom]["avg_us"],
-                     "bytes_per_launch": d["bytes"] // d["launches"]},
+                     "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": traffic, "kernel": dom,
+                     "avg_us": kernels[dom]["avg_us"], "bytes_per_launch": d["bytes"] // d["launches"]},
         "kernels": kernels,
     }
+
+
+def run_precision(qd, dims, gates, precision, upload, steps, warmup, modes):
+    import torch
+
+    st = qd.State(dims, precision, init=None)
+    ab = 16 if precision == "c128" else 8
+    best_ms = st.copy_ceiling(3)
+    ceiling = 2 * st.D * ab / (best_ms * 1e-3) / 1e9
+    log(f"{precision}: copy ceiling {ceiling:.1f} GB/s ({best_ms:.3f} ms per read+rewrite pass)")
+    out = {"copy_ceiling_GBps": round(ceiling, 1)}
+    for mode in modes:
+        t0 = time.time()
+        upload(st)
+        st.synchronize()
+        log(f"{precision}: state uploaded in {time.time() - t0:.1f} s")
+        out[mode] = run_mode(qd, st, dims, gates, precision, mode, steps, warmup)
     st.close()
     del st
     torch.cuda.empty_cache()
     return out
 
 
-def cpu_baseline(dims, gates, psi, infos, seconds):
+def cpu_baseline(qd, dims, gates, psi, seconds):
     import oracle
 
     done, updates = 0, 0
     t0 = time.perf_counter()
-    for g, info in zip(gates, infos):
+    for g in gates:
         oracle.apply_gate(dims, psi, g)
         done += 1
-        updates += info["updated"]
+        updates += qd.gate_info(dims, g.targets, g.U, g.controls, g.values, "c128")["updated"]
         if time.perf_counter() - t0 >= seconds:
             break
     dt = time.perf_counter() - t0
@@ -147,10 +216,13 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--gates", type=int, default=500)
-    ap.add_argument("--no-c64", action="store_true", help="skip the complex64 run")
+    ap.add_argument("--modes", default="fused,plain", help="comma list of fused, plain")
+    ap.add_argument("--no-c64", action="store_true", help="skip the complex64 runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--small", action="store_true", help="2^10 x 3^6 x 4^2 register (quick check)")
+    ap.add_argument("--tile-c128", type=int, default=0, help="fused tile size, c128 (0 = library default)")
+    ap.add_argument("--tile-c64", type=int, default=0, help="fused tile size, c64 (0 = library default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported (the sharded multi-GPU "
@@ -170,6 +242,8 @@ def main() -> int:
     _, gates = circuits.large(n_gates=args.gates, dims=dims)
     D = math.prod(dims)
     G = states.GaussianState(D, seed=circuits.SEEDS["large"])
+    modes = [m for m in args.modes.split(",") if m]
+    TILE["c128"], TILE["c64"] = args.tile_c128, args.tile_c64
     t0 = time.time()
     host = None
     if not args.no_cpu_baseline:
@@ -186,18 +260,19 @@ def main() -> int:
         else:
             G.fill(lambda start, vals: st.set_interleaved(vals, start))
 
-    res = {"c128": run_precision(qd, dims, gates, "c128", upload, args.steps, args.warmup)}
+    res = {"c128": run_precision(qd, dims, gates, "c128", upload, args.steps, args.warmup, modes)}
     if not args.no_c64:
-        res["c64"] = run_precision(qd, dims, gates, "c64", upload, args.steps, args.warmup)
+        res["c64"] = run_precision(qd, dims, gates, "c64", upload, args.steps, args.warmup, modes)
     cpu = None
     if host is not None:
-        infos = [qd.gate_info(dims, g.targets, g.U, g.controls, g.values, "c128") for g in gates]
-        cpu = cpu_baseline(dims, gates, host, infos, args.cpu_seconds)
+        cpu = cpu_baseline(qd, dims, gates, host, args.cpu_seconds)
         log(f"cpu baseline: {cpu['value']:.3e} updates/s ({cpu['sample']})")
 
-    h = res["c128"]
+    head_mode = modes[0]
+    h = res["c128"][head_mode]
     workload = (f"large: dims {'2^10 x 3^6 x 4^2' if args.small else '2^14 x 3^8 x 4^2'} (D={D}), complex128, "
-                f"{len(gates)}-gate circuit (seed {circuits.SEEDS['large']}), Gaussian initial state in HBM")
+                f"{len(gates)}-gate circuit (seed {circuits.SEEDS['large']}), Gaussian initial state in HBM, "
+                f"{head_mode} path")
     line = {
         "metric": "gate-amplitude updates/s",
         "value": h["value"],
@@ -211,18 +286,25 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": workload, "D": D, "gates": len(gates), "precision": "c128"},
-        "algorithmic_GBps": h["algorithmic_GBps"],
+        "config": {"workload": workload, "D": D, "gates": len(gates), "precision": "c128", "path": head_mode},
         "roofline": h["roofline"],
         "cpu_baseline": cpu,
-        "kernels": h["kernels"],
+        "copy_ceiling_GBps": {p: res[p]["copy_ceiling_GBps"] for p in res},
         "norm_last_step": h["norm_last_step"],
+        "launches_per_step": h["launches_per_step"],
+        "kernels": h["kernels"],
+        "runs": {},
     }
-    if "c64" in res:
-        c = res["c64"]
-        line["c64"] = {"value": c["value"], "unit": "updates/s", "dtype": "f32", "ms_per_step": c["ms_per_step"],
-                       "algorithmic_GBps": c["algorithmic_GBps"], "roofline": c["roofline"],
-                       "norm_last_step": c["norm_last_step"], "kernels": c["kernels"]}
+    for p in res:
+        for m in modes:
+            if p == "c128" and m == head_mode:
+                continue
+            r = res[p][m]
+            line["runs"][f"{m}_{p}"] = {"value": r["value"], "unit": "updates/s",
+                                        "dtype": "f64" if p == "c128" else "f32",
+                                        "ms_per_step": r["ms_per_step"], "launches_per_step": r["launches_per_step"],
+                                        "roofline": r["roofline"], "norm_last_step": r["norm_last_step"],
+                                        "kernels": r["kernels"]}
     print(json.dumps(line), flush=True)
     return 0
 

@@ -154,6 +154,44 @@ int qd_state_info(const qd_state* s, uint64_t* D, int32_t* precision, void** dev
 int qd_apply_gate(qd_state* s, const int32_t* targets, int32_t k, const int32_t* controls,
                   const int32_t* values, int32_t m, const double* U);
 
+/* One gate of a gate list: the arguments of qd_apply_gate. */
+typedef struct {
+    const int32_t* targets;
+    int32_t k;
+    const int32_t* controls;
+    const int32_t* values;
+    int32_t m;
+    const double* U;
+} qd_gate_desc;
+
+typedef struct {
+    int32_t fuse;         /* 1 (default when opts is null): LDS-staged fusion of consecutive gates;
+                             0: one sweep per gate, exactly as qd_apply_gate */
+    int32_t tile_amps;    /* largest tile of a fused pass in amplitudes; 0 = 4096 (c128) / 8192 (c64);
+                             at most 32768 and at most 160 KB of LDS */
+    int32_t min_run;      /* contiguous run a tile must hold, in amplitudes; 0 = 64 (c128) / 128 (c64) */
+    int32_t passes;       /* out: HBM passes enqueued */
+    int32_t fused_passes; /* out: how many of them were fused passes */
+} qd_circuit_options;
+
+/* Apply gates[0..count-1] in order, in place and asynchronously. Every gate is
+ * validated (as qd_check_gate) before any work is enqueued, so an invalid gate
+ * leaves the state untouched. With fusion, runs of consecutive gates whose
+ * targets fit one tile are applied in one HBM pass: a workgroup loads a tile (all
+ * amplitudes over a small qudit set for one value of the other digits) into LDS,
+ * applies the gates of the run in order with the same per-class arithmetic as
+ * qd_apply_gate, and writes it back once (Sec. 2.3: each gate maps every class,
+ * hence every tile, to itself). The result is bitwise the same as applying the
+ * gates one by one. Gates are never reordered. opts may be null. */
+int qd_apply_circuit(qd_state* s, const qd_gate_desc* gates, int32_t count, qd_circuit_options* opts);
+
+/* Host-only: the passes qd_apply_circuit would enqueue for this register and
+ * gate list. pass_gates[i] = gates in pass i, pass_tile[i] = tile amplitudes of
+ * a fused pass or 0 for a one-gate sweep; both may be null, else they need room
+ * for `count` entries. *npasses receives the number of passes. */
+int qd_circuit_plan(const int32_t* dims, int32_t n, int32_t precision, const qd_gate_desc* gates, int32_t count,
+                    const qd_circuit_options* opts, int32_t* pass_gates, int32_t* pass_tile, int32_t* npasses);
+
 /* ||psi||_2 = sqrt(sum_j |a_j|^2), summed in FP64 on the device in a fixed
  * order (the same result for the same state, run after run). Synchronous. */
 int qd_norm(const qd_state* s, double* out);
@@ -166,6 +204,15 @@ int qd_probabilities(const qd_state* s, double* out, uint64_t len, int32_t locat
 
 /* Wait for the state's queued work; reports asynchronous device errors. */
 int qd_synchronize(const qd_state* s);
+
+/* ---- measurement -------------------------------------------------------------- */
+
+/* Read and rewrite every amplitude of the state once, in place, `reps` times
+ * (after one warm-up pass), with the access pattern of the gate sweeps; values
+ * are unchanged (multiplied by a run-time 1.0). *best_ms receives the fastest
+ * pass in milliseconds, so 2 * D * bytes-per-amplitude / best_ms is the
+ * read+write copy ceiling the sweeps are measured against. Synchronous. */
+int qd_copy_ceiling(qd_state* s, int32_t reps, double* best_ms);
 
 /* ---- misc -------------------------------------------------------------------- */
 

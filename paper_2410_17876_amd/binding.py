@@ -30,6 +30,16 @@ class QDError(RuntimeError):
         self.code = code
 
 
+class GateDesc(C.Structure):
+    _fields_ = [("targets", C.POINTER(C.c_int32)), ("k", C.c_int32), ("controls", C.POINTER(C.c_int32)),
+                ("values", C.POINTER(C.c_int32)), ("m", C.c_int32), ("U", C.POINTER(C.c_double))]
+
+
+class CircuitOptions(C.Structure):
+    _fields_ = [("fuse", C.c_int32), ("tile_amps", C.c_int32), ("min_run", C.c_int32), ("passes", C.c_int32),
+                ("fused_passes", C.c_int32)]
+
+
 class GateInfo(C.Structure):
     _fields_ = [("kernel", C.c_char * 64), ("category", C.c_int32), ("M", C.c_int32), ("classes", C.c_uint64),
                 ("updated", C.c_uint64), ("bytes", C.c_uint64), ("flops", C.c_uint64)]
@@ -61,6 +71,10 @@ def _load() -> C.CDLL:
         "qd_norm": [vp, f64p],
         "qd_probabilities": [vp, f64p, C.c_uint64, C.c_int32],
         "qd_synchronize": [vp],
+        "qd_copy_ceiling": [vp, C.c_int32, f64p],
+        "qd_apply_circuit": [vp, C.POINTER(GateDesc), C.c_int32, C.POINTER(CircuitOptions)],
+        "qd_circuit_plan": [i32p, C.c_int32, C.c_int32, C.POINTER(GateDesc), C.c_int32, C.POINTER(CircuitOptions),
+                            i32p, i32p, i32p],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -92,6 +106,44 @@ def _u(U) -> tuple:
     if a.ndim != 2 or a.shape[0] != a.shape[1]:
         raise ValueError("U must be a square matrix")
     return a, a.view(np.float64).ctypes.data_as(C.POINTER(C.c_double))
+
+
+class GateList:
+    """A gate list marshalled once into qd_gate_desc records (keeps the arrays alive)."""
+
+    def __init__(self, gates):
+        self.gates = list(gates)
+        self._keep = []
+        self.descs = (GateDesc * max(1, len(self.gates)))()
+        for i, g in enumerate(self.gates):
+            t, tp = _i32(g.targets)
+            c, cp = _i32(g.controls)
+            v, vp_ = _i32(g.values)
+            u, up = _u(g.U)
+            self._keep += [t, c, v, u]
+            self.descs[i] = GateDesc(tp, len(g.targets), cp, vp_, len(g.controls), up)
+
+    def __len__(self):
+        return len(self.gates)
+
+
+def _options(fuse=True, tile_amps=0, min_run=0) -> CircuitOptions:
+    return CircuitOptions(1 if fuse else 0, int(tile_amps), int(min_run), 0, 0)
+
+
+def circuit_plan(dims, gates, precision="c128", fuse=True, tile_amps=0, min_run=0):
+    """Passes qd_apply_circuit would enqueue: list of (gates in pass, tile amplitudes or 0)."""
+    gl = gates if isinstance(gates, GateList) else GateList(gates)
+    d, dp = _i32(dims)
+    n = len(gl)
+    pg = np.zeros(max(1, n), dtype=np.int32)
+    pt = np.zeros(max(1, n), dtype=np.int32)
+    npass = C.c_int32()
+    opts = _options(fuse, tile_amps, min_run)
+    check(lib.qd_circuit_plan(dp, len(dims), PRECISIONS[precision], gl.descs, n, C.byref(opts),
+                              pg.ctypes.data_as(C.POINTER(C.c_int32)), pt.ctypes.data_as(C.POINTER(C.c_int32)),
+                              C.byref(npass)))
+    return [(int(pg[i]), int(pt[i])) for i in range(npass.value)]
 
 
 def dim(dims: Sequence[int]) -> int:
@@ -188,6 +240,13 @@ class State:
             self.apply_gate(g)
         return self
 
+    def run_circuit(self, gates, fuse=True, tile_amps=0, min_run=0) -> dict:
+        """Apply a gate list through qd_apply_circuit; returns the pass counts."""
+        gl = gates if isinstance(gates, GateList) else GateList(gates)
+        opts = _options(fuse, tile_amps, min_run)
+        check(lib.qd_apply_circuit(self._h, gl.descs, len(gl), C.byref(opts)))
+        return {"passes": opts.passes, "fused_passes": opts.fused_passes}
+
     def norm(self) -> float:
         out = C.c_double()
         check(lib.qd_norm(self._h, C.byref(out)))
@@ -225,6 +284,12 @@ class State:
         v = np.ascontiguousarray(values, dtype=np.float64)
         check(lib.qd_state_set_amplitudes(self._h, v.ctypes.data_as(C.POINTER(C.c_double)), offset, v.size // 2))
         return self
+
+    def copy_ceiling(self, reps: int = 3) -> float:
+        """Fastest in-place read+rewrite pass over the state, in ms (values unchanged)."""
+        out = C.c_double()
+        check(lib.qd_copy_ceiling(self._h, int(reps), C.byref(out)))
+        return out.value
 
     def synchronize(self) -> None:
         check(lib.qd_synchronize(self._h))

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/qd.h"
+#include "fusion.h"
 #include "kernels.h"
 #include "plan.h"
 #include "planner.h"
@@ -332,6 +333,74 @@ int qd_state_get_amplitudes(const qd_state* s, double* host, uint64_t offset, ui
     return QD_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Copy `bytes` of per-launch data to the device through the state's ring.
+int stage(qd_state* s, const void* data, size_t bytes, const void** dptr) {
+    if (bytes > GateRing::kSlot) return set_err(QD_ERR_NOT_SUPPORTED, "per-launch gate data exceeds the staging slot");
+    int rc = s->ring.ensure();
+    if (rc) return rc;
+    GateRing& r = s->ring;
+    const int slot = r.next;
+    r.next = (r.next + 1) % GateRing::kSlots;
+    if (r.pending[slot]) QD_HIP(hipEventSynchronize(r.ev[slot]), "gate staging");
+    unsigned char* h = r.host + slot * GateRing::kSlot;
+    unsigned char* d = r.dev + slot * GateRing::kSlot;
+    std::memcpy(h, data, bytes);
+    QD_HIP(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, s->stream), "gate upload");
+    QD_HIP(hipEventRecord(r.ev[slot], s->stream), "gate staging");
+    r.pending[slot] = true;
+    *dptr = d;
+    return QD_OK;
+}
+
+int enqueue_single(qd_state* s, const GatePlan& p, const double* U) {
+    const size_t gbytes = device_gate_bytes(p, s->precision);
+    const void* dgate = nullptr;
+    if (gbytes) {
+        std::vector<unsigned char> buf(gbytes);
+        fill_device_gate(p, s->precision, U, buf.data());
+        int rc = stage(s, buf.data(), gbytes, &dgate);
+        if (rc) return rc;
+    }
+    QD_HIP(launch_gate(p, s->precision, s->psi, U, dgate, s->stream), "gate launch");
+    return QD_OK;
+}
+
+int circuit_options(const qd_circuit_options* o, int precision, CircuitOptions* co) {
+    co->fuse = o ? o->fuse != 0 : true;
+    const uint64_t tile = (o && o->tile_amps > 0) ? (uint64_t)o->tile_amps : (precision == QD_C128 ? 4096 : 8192);
+    const uint64_t run = (o && o->min_run > 0) ? (uint64_t)o->min_run : (precision == QD_C128 ? 64 : 128);
+    if (tile > 32768) return set_err(QD_ERR_INVALID_ARGUMENT, "tile_amps must be at most 32768");
+    if (tile * amp_bytes(precision) > 160 * 1024)
+        return set_err(QD_ERR_INVALID_ARGUMENT, "a tile must fit the 160 KB of LDS");
+    co->tile_max = tile;
+    co->min_run = run;
+    return QD_OK;
+}
+
+int circuit_gates(const int32_t* dims, int32_t n, const qd_gate_desc* gates, int32_t count,
+                  std::vector<CircuitGate>& cg) {
+    if (count < 0) return set_err(QD_ERR_INVALID_ARGUMENT, "negative gate count");
+    if (count > 0 && !gates) return set_err(QD_ERR_INVALID_ARGUMENT, "gates is null");
+    cg.resize(count);
+    for (int i = 0; i < count; ++i) {
+        const qd_gate_desc& g = gates[i];
+        std::string err;
+        int rc = check_gate(dims, n, g.targets, g.k, g.controls, g.values, g.m, &err);
+        if (rc) return set_err(rc, "gate " + std::to_string(i) + ": " + err);
+        if (!g.U) return set_err(QD_ERR_INVALID_ARGUMENT, "gate " + std::to_string(i) + ": U is null");
+        cg[i] = CircuitGate{g.targets, g.k, g.controls, g.values, g.m, g.U};
+    }
+    return QD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int qd_apply_gate(qd_state* s, const int32_t* targets, int32_t k, const int32_t* controls, const int32_t* values,
                   int32_t m, const double* U) {
     if (!s) return set_err(QD_ERR_INVALID_ARGUMENT, "state is null");
@@ -341,24 +410,70 @@ int qd_apply_gate(qd_state* s, const int32_t* targets, int32_t k, const int32_t*
     if (rc) return set_err(rc, err);
     rc = use_device(s);
     if (rc) return rc;
-    const size_t gbytes = device_gate_bytes(p, s->precision);
-    const void* dgate = nullptr;
-    if (gbytes) {
-        rc = s->ring.ensure();
-        if (rc) return rc;
-        GateRing& r = s->ring;
-        const int slot = r.next;
-        r.next = (r.next + 1) % GateRing::kSlots;
-        if (r.pending[slot]) QD_HIP(hipEventSynchronize(r.ev[slot]), "gate staging");
-        unsigned char* h = r.host + slot * GateRing::kSlot;
-        unsigned char* d = r.dev + slot * GateRing::kSlot;
-        fill_device_gate(p, s->precision, U, h);
-        QD_HIP(hipMemcpyAsync(d, h, gbytes, hipMemcpyHostToDevice, s->stream), "gate upload");
-        QD_HIP(hipEventRecord(r.ev[slot], s->stream), "gate staging");
-        r.pending[slot] = true;
-        dgate = d;
+    return enqueue_single(s, p, U);
+}
+
+int qd_circuit_plan(const int32_t* dims, int32_t n, int32_t precision, const qd_gate_desc* gates, int32_t count,
+                    const qd_circuit_options* opts, int32_t* pass_gates, int32_t* pass_tile, int32_t* npasses) {
+    int rc = check_precision(precision);
+    if (rc) return rc;
+    std::string err;
+    rc = check_dims(dims, n, nullptr, &err);
+    if (rc) return set_err(rc, err);
+    if (!npasses) return set_err(QD_ERR_INVALID_ARGUMENT, "npasses is null");
+    std::vector<CircuitGate> cg;
+    rc = circuit_gates(dims, n, gates, count, cg);
+    if (rc) return rc;
+    CircuitOptions co;
+    rc = circuit_options(opts, precision, &co);
+    if (rc) return rc;
+    std::vector<PassPlan> plan;
+    rc = plan_circuit(dims, n, precision, cg.data(), count, co, plan, &err);
+    if (rc) return set_err(rc, err);
+    *npasses = (int32_t)plan.size();
+    for (size_t i = 0; i < plan.size(); ++i) {
+        if (pass_gates) pass_gates[i] = plan[i].fused ? plan[i].launch.ngates : 1;
+        if (pass_tile) pass_tile[i] = plan[i].fused ? (int32_t)plan[i].launch.tile : 0;
     }
-    QD_HIP(launch_gate(p, s->precision, s->psi, U, dgate, s->stream), "gate launch");
+    return QD_OK;
+}
+
+int qd_apply_circuit(qd_state* s, const qd_gate_desc* gates, int32_t count, qd_circuit_options* opts) {
+    if (!s) return set_err(QD_ERR_INVALID_ARGUMENT, "state is null");
+    std::vector<CircuitGate> cg;
+    int rc = circuit_gates(s->dims, s->n, gates, count, cg);
+    if (rc) return rc;
+    CircuitOptions co;
+    rc = circuit_options(opts, s->precision, &co);
+    if (rc) return rc;
+    std::vector<PassPlan> plan;
+    std::string err;
+    rc = plan_circuit(s->dims, s->n, s->precision, cg.data(), count, co, plan, &err);
+    if (rc) return set_err(rc, err);
+    rc = use_device(s);
+    if (rc) return rc;
+    int fused = 0;
+    GatePlan p;
+    for (const PassPlan& pp : plan) {
+        if (!pp.fused) {
+            const CircuitGate& g = cg[pp.gates[0]];
+            rc = plan_gate(s->dims, s->n, g.targets, g.k, g.controls, g.values, g.m, g.U, &p, &err);
+            if (rc) return set_err(rc, err);
+            rc = enqueue_single(s, p, g.U);
+            if (rc) return rc;
+            continue;
+        }
+        if (pp.launch.ngates == 0) continue;
+        const void* dblob = nullptr;
+        rc = stage(s, pp.blob.data(), pp.blob.size(), &dblob);
+        if (rc) return rc;
+        QD_HIP(launch_fused(pp.launch, s->precision, s->psi, dblob, s->stream), "fused launch");
+        ++fused;
+    }
+    if (opts) {
+        opts->passes = (int32_t)plan.size();
+        opts->fused_passes = fused;
+    }
     return QD_OK;
 }
 
@@ -408,6 +523,32 @@ int qd_probabilities(const qd_state* s, double* out, uint64_t len, int32_t locat
         }
     }
     (void)hipFree(tmp);
+    return QD_OK;
+}
+
+int qd_copy_ceiling(qd_state* s, int32_t reps, double* best_ms) {
+    if (!s || !best_ms) return set_err(QD_ERR_INVALID_ARGUMENT, "state or best_ms is null");
+    if (reps < 1) return set_err(QD_ERR_INVALID_ARGUMENT, "reps must be >= 1");
+    int rc = use_device(s);
+    if (rc) return rc;
+    hipEvent_t a, b;
+    QD_HIP(hipEventCreate(&a), "event");
+    QD_HIP(hipEventCreate(&b), "event");
+    float best = -1.0f;
+    hipError_t e = launch_stream_rewrite(s->psi, s->precision, s->D, s->stream);  // warm-up
+    for (int i = 0; i < reps && e == hipSuccess; ++i) {
+        e = hipEventRecord(a, s->stream);
+        if (e == hipSuccess) e = launch_stream_rewrite(s->psi, s->precision, s->D, s->stream);
+        if (e == hipSuccess) e = hipEventRecord(b, s->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+        if (e == hipSuccess && (best < 0.0f || ms < best)) best = ms;
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (e != hipSuccess) return hip_err(e, "copy ceiling");
+    *best_ms = best;
     return QD_OK;
 }
 

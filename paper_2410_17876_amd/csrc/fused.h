@@ -1,0 +1,64 @@
+// fused.h - LDS-staged fusion of consecutive gates: the data a fused pass hands
+// to its kernel.
+//
+// A fused pass picks a set S of qudits: the lowest qudits (so that the tile is
+// made of contiguous runs of L amplitudes) plus every target of the gates in the
+// pass. A tile is the M_S = prod_{q in S} d_q amplitudes that share one value of
+// every digit outside S; tiles are disjoint and every gate of the pass maps each
+// tile to itself, because each gate's classes (Sec. 2.3) only vary target digits.
+// A workgroup loads one tile into LDS, applies the gates of the pass in order to
+// the tile, and writes the tile back once, so the pass costs one HBM read and
+// one HBM write of the state instead of one per gate.
+//
+// Inside the tile, amplitudes are ordered by the S digits in increasing qudit
+// order, so the tile is itself a small mixed-radix register and each gate gets
+// an ordinary class plan over it. A control on a qudit inside S is a control of
+// that tile-local plan; a control on a qudit outside S is constant over a tile
+// and becomes a per-tile predicate on the tile's base address.
+#pragma once
+
+#include <stdint.h>
+
+#include "plan.h"
+
+namespace qd {
+
+constexpr int kTileMaxSeg = 8;      // free segments of a tile-local plan
+constexpr int kFuseMaxM = 16;       // class size (dense) / active count (monomial) inside a tile
+constexpr int kFuseMaxGates = 64;   // gates per fused pass
+constexpr int kMaxOuterCtl = 8;     // controls outside S per gate
+constexpr int kFuseBlock = 256;
+
+// A gate's classes inside a tile are the same for every tile, so their tile-local
+// bases are computed once on the host (uint16: a tile has at most 32768
+// amplitudes) instead of being decoded per class and per tile on the device.
+struct TileGate {
+    int32_t kind;        // kDense, or kMonomial for monomial and diagonal gates
+    int32_t M;           // dense: class size; monomial: number of active entries
+    uint32_t n_classes;                 // classes of the gate inside one tile
+    uint32_t bases_off;                 // byte offset of the uint16 class bases in the blob
+    uint32_t off[kFuseMaxM];            // dense: member offsets; monomial: source offsets
+    uint32_t dst[kFuseMaxM];            // monomial: destination offsets
+    uint32_t one_mask;                  // monomial: bit i set if factor i is exactly 1
+    int32_t n_outer;                    // controls outside S
+    uint64_t oc_stride[kMaxOuterCtl];   // the gate runs on a tile iff for every l:
+    uint32_t oc_dim[kMaxOuterCtl];      //   (tile base / oc_stride[l]) mod oc_dim[l] == oc_val[l]
+    uint32_t oc_val[kMaxOuterCtl];
+    uint32_t u_off;                     // byte offset of U (dense) or the factors (monomial) in the blob
+};
+
+// Scalar kernel arguments of a fused pass. The device arrays (gate descriptors,
+// gate data, run offsets) are separate `const __restrict__` kernel parameters so
+// that the compiler may read them through the scalar cache.
+template <typename I>
+struct FusedArgs {
+    Decode<I> outer;                    // tile id -> base address of the tile
+    uint32_t tile;                      // amplitudes per tile (M_S)
+    uint32_t L;                         // contiguous run length
+    uint32_t chunks_per_run;            // ceil(L / 64): wavefront-sized pieces of a run
+    uint32_t nchunks;                   // runs * chunks_per_run
+    FastDiv<uint32_t> cdiv;             // division by chunks_per_run
+    int32_t ngates;
+};
+
+}  // namespace qd

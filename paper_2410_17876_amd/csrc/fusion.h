@@ -1,0 +1,40 @@
+// fusion.h - host-side planning of gate lists into HBM passes (fusion.cpp).
+#pragma once
+
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "fused.h"
+#include "kernels.h"
+#include "planner.h"
+
+namespace qd {
+
+struct CircuitGate {
+    const int32_t* targets;
+    int k;
+    const int32_t* controls;
+    const int32_t* values;
+    int m;
+    const double* U;
+};
+
+struct CircuitOptions {
+    bool fuse = true;
+    uint64_t tile_max = 4096;  // amplitudes per tile
+    uint64_t min_run = 64;     // minimum contiguous run inside a tile
+};
+
+struct PassPlan {
+    bool fused = false;
+    std::vector<int> gates;           // indices into the gate list, in order
+    FusedLaunch launch;               // fused passes
+    std::vector<unsigned char> blob;  // fused passes: device data, built for one precision
+};
+
+int plan_circuit(const int32_t* dims, int n, int precision, const CircuitGate* gates, int count,
+                 const CircuitOptions& opt, std::vector<PassPlan>& out, std::string* err);
+
+}  // namespace qd

@@ -28,6 +28,23 @@ void fill_device_gate(const GatePlan& p, int precision, const double* U, void* d
 hipError_t launch_gate(const GatePlan& p, int precision, void* psi, const double* U, const void* dgate,
                        hipStream_t stream);
 
+// A fused pass (fused.h, fused.hip). The device blob holds the TileGate array
+// at gates_off, the rounded gate data the descriptors point into, and the run
+// offsets (32-bit when D < 2^31, else 64-bit) at run_off_off.
+struct FusedLaunch {
+    uint64_t D;
+    uint64_t n_tiles;
+    int outer_nseg;
+    uint64_t outer_size[kMaxSeg];
+    uint64_t outer_stride[kMaxSeg];
+    uint32_t tile;
+    uint32_t L;
+    int ngates;
+    size_t gates_off;
+    size_t run_off_off;
+};
+hipError_t launch_fused(const FusedLaunch& f, int precision, void* psi, const void* dblob, hipStream_t stream);
+
 // Reductions and fills (reduce.hip).
 constexpr int kRedBlocks = 1024;
 hipError_t launch_sumsq(const void* psi, int precision, uint64_t D, double* scratch /* kRedBlocks+1 */,
@@ -35,5 +52,6 @@ hipError_t launch_sumsq(const void* psi, int precision, uint64_t D, double* scra
 hipError_t launch_probabilities(const void* psi, int precision, uint64_t offset, uint64_t count,
                                 double* out, hipStream_t stream);
 hipError_t launch_basis(void* psi, int precision, uint64_t D, uint64_t j, hipStream_t stream);
+hipError_t launch_stream_rewrite(void* psi, int precision, uint64_t D, hipStream_t stream);
 
 }  // namespace qd

@@ -82,26 +82,34 @@ inline FastDiv<I> make_fast_div(uint64_t G) {
 
 // Class-id -> base decoder. Segment nseg-1 is the most significant and needs no
 // division (c < n_classes bounds its digit).
-template <typename I>
+template <typename I, int NS = kMaxSeg>
 struct Decode {
     I n_classes;
     I ctrl_off;
     int32_t nseg;
-    I size[kMaxSeg];
-    I stride[kMaxSeg];
-    FastDiv<I> div[kMaxSeg];
+    I size[NS];
+    I stride[NS];
+    FastDiv<I> div[NS];
 };
 
-template <typename I>
-__host__ __device__ inline I decode_base(const Decode<I>& dec, I c) {
+// The loop is unrolled to the compile-time bound and every step is guarded
+// instead of exiting early, so every table access has a constant index (scalar
+// registers or scalar loads on the device, never a dynamically indexed private
+// array). `last` is uniform, so the guards are uniform branches.
+template <typename I, int NS>
+__host__ __device__ inline I decode_base(const Decode<I, NS>& dec, I c) {
     I base = dec.ctrl_off;
     const int last = dec.nseg - 1;
-    for (int g = 0; g < last; ++g) {
-        I q = fast_div<I>(c, dec.div[g]);
-        base += (c - q * dec.size[g]) * dec.stride[g];
-        c = q;
+#pragma unroll
+    for (int g = 0; g < NS; ++g) {
+        if (g < last) {
+            const I q = fast_div<I>(c, dec.div[g]);
+            base += (c - q * dec.size[g]) * dec.stride[g];
+            c = q;
+        } else if (g == last) {
+            base += c * dec.stride[g];
+        }
     }
-    if (last >= 0) base += c * dec.stride[last];
     return base;
 }
 
@@ -127,13 +135,13 @@ struct GatePlan {
     uint8_t lam_one[kMaxM];
 };
 
-template <typename I>
-inline Decode<I> make_decode(const GatePlan& p) {
-    Decode<I> d;
+template <typename I, int NS = kMaxSeg>
+inline Decode<I, NS> make_decode(const GatePlan& p) {
+    Decode<I, NS> d;
     d.n_classes = (I)p.n_classes;
     d.ctrl_off = (I)p.ctrl_off;
     d.nseg = p.nseg;
-    for (int g = 0; g < kMaxSeg; ++g) {
+    for (int g = 0; g < NS; ++g) {
         d.size[g] = g < p.nseg ? (I)p.seg_size[g] : (I)1;
         d.stride[g] = g < p.nseg ? (I)p.seg_stride[g] : (I)0;
         d.div[g] = make_fast_div<I>(g < p.nseg ? p.seg_size[g] : 1);

@@ -29,6 +29,30 @@ static int fail(std::string* err, int code, const char* fmt, ...) {
     return code;
 }
 
+bool free_segments(const int32_t* dims, int n, const bool* special, int* nseg, uint64_t* size, uint64_t* stride,
+                   uint64_t* n_free) {
+    // Maximal runs of consecutive non-special qudits, least significant first.
+    uint64_t s = 1, prod = 1;
+    int ns = 0;
+    for (int i = 0; i < n; ++i) {
+        if (!special[i]) {
+            if (i > 0 && !special[i - 1] && ns > 0) {
+                size[ns - 1] *= (uint64_t)dims[i];
+            } else {
+                if (ns >= kMaxSeg) return false;
+                size[ns] = (uint64_t)dims[i];
+                stride[ns] = s;
+                ++ns;
+            }
+            prod *= (uint64_t)dims[i];
+        }
+        s *= (uint64_t)dims[i];
+    }
+    *nseg = ns;
+    *n_free = prod;
+    return true;
+}
+
 int check_dims(const int32_t* dims, int32_t n, uint64_t* D, std::string* err) {
     if (!dims) return fail(err, QD_ERR_INVALID_ARGUMENT, "dims is null");
     if (n < 1 || n > QD_MAX_QUDITS)
@@ -106,21 +130,8 @@ int plan_gate(const int32_t* dims, int32_t n, const int32_t* targets, int32_t k,
         special[controls[l]] = true;
         p->ctrl_off += (uint64_t)values[l] * s[controls[l]];
     }
-    // Free-qudit segments, least significant first.
-    p->nseg = 0;
-    p->n_classes = 1;
-    for (int i = 0; i < n; ++i) {
-        if (special[i]) continue;
-        if (i > 0 && !special[i - 1] && p->nseg > 0) {
-            p->seg_size[p->nseg - 1] *= (uint64_t)dims[i];
-        } else {
-            if (p->nseg >= kMaxSeg) return fail(err, QD_ERR_NOT_SUPPORTED, "too many free-qudit segments");
-            p->seg_size[p->nseg] = (uint64_t)dims[i];
-            p->seg_stride[p->nseg] = s[i];
-            ++p->nseg;
-        }
-        p->n_classes *= (uint64_t)dims[i];
-    }
+    if (!free_segments(dims, n, special, &p->nseg, p->seg_size, p->seg_stride, &p->n_classes))
+        return fail(err, QD_ERR_NOT_SUPPORTED, "too many free-qudit segments");
     // Member offsets: local index a -> sum_l a_l s_{t_l}, first target least significant.
     for (int a = 0; a < M; ++a) {
         int rest = a;

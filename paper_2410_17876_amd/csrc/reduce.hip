@@ -71,6 +71,35 @@ __global__ __launch_bounds__(256) void basis_fill(T* __restrict__ psi, uint64_t 
     }
 }
 
+// Read and rewrite every amplitude once, in place, with the access pattern of
+// the gate sweeps (one 8/16-byte element per thread, non-temporal, XCD-contiguous
+// blocks). `one` is 1.0 at run time, so the values are unchanged; the kernel is
+// the read+write copy ceiling the sweeps are compared against and the known-size
+// reference for HBM counter calibration.
+template <typename R>
+__global__ __launch_bounds__(256) void stream_rewrite(R __attribute__((ext_vector_type(2))) * __restrict__ psi,
+                                                      uint64_t D, R one) {
+    const uint32_t G = gridDim.x, b = blockIdx.x, q = G >> 3, r = G & 7u, x = b & 7u;
+    const uint64_t blk = (uint64_t)(x * q + (x < r ? x : r) + (b >> 3));
+    const uint64_t i = blk * 256 + threadIdx.x;
+    if (i < D) {
+        auto v = __builtin_nontemporal_load(psi + i);
+        __builtin_nontemporal_store(v * one, psi + i);
+    }
+}
+
+hipError_t launch_stream_rewrite(void* psi, int precision, uint64_t D, hipStream_t st) {
+    const uint64_t blocks = (D + 255) / 256;
+    if (blocks > 0x7fffffffull) return hipErrorInvalidValue;
+    if (precision == kC128)
+        hipLaunchKernelGGL(stream_rewrite<double>, dim3((unsigned)blocks), dim3(256), 0, st,
+                           static_cast<double __attribute__((ext_vector_type(2)))*>(psi), D, 1.0);
+    else
+        hipLaunchKernelGGL(stream_rewrite<float>, dim3((unsigned)blocks), dim3(256), 0, st,
+                           static_cast<float __attribute__((ext_vector_type(2)))*>(psi), D, 1.0f);
+    return hipGetLastError();
+}
+
 static unsigned grid_for(uint64_t n) {
     const uint64_t b = (n + 255) / 256;
     return (unsigned)(b < 8192 ? (b ? b : 1) : 8192);

@@ -32,33 +32,13 @@
 #include <algorithm>
 #include <cstring>
 
+#include "device.h"
 #include "kernels.h"
 #include "plan.h"
 
 namespace qd {
 
-template <typename R>
-struct Cx {
-    using T = R __attribute__((ext_vector_type(2)));
-};
-
 constexpr int kBlock = 256;
-
-template <typename T>
-__device__ __forceinline__ T ld_stream(const T* p) {
-    return __builtin_nontemporal_load(p);
-}
-template <typename T>
-__device__ __forceinline__ void st_stream(T* p, T v) {
-    __builtin_nontemporal_store(v, p);
-}
-
-// Workgroup b runs on XCD b % 8. Renumber so that XCD x takes one contiguous
-// range of logical blocks (a bijection on [0, gridDim.x)).
-__device__ __forceinline__ uint32_t xcd_block() {
-    const uint32_t G = gridDim.x, b = blockIdx.x, q = G >> 3, r = G & 7u, x = b & 7u;
-    return x * q + (x < r ? x : r) + (b >> 3);
-}
 
 template <typename I, int M>
 struct Offs {
@@ -73,10 +53,7 @@ struct UArg<R, M, true> {
     __device__ __forceinline__ typename Cx<R>::T get(int i) const { return u[i]; }
 };
 template <typename R, int M>
-struct UArg<R, M, false> {
-    const typename Cx<R>::T* __restrict__ u;
-    __device__ __forceinline__ typename Cx<R>::T get(int i) const { return u[i]; }
-};
+struct UArg<R, M, false> {};  // U comes as the kernel's Ug parameter
 
 template <int M>
 constexpr int dense_v() {
@@ -86,7 +63,8 @@ constexpr int dense_v() {
 template <typename R, int M, typename I, int V, bool INL>
 __global__ __launch_bounds__(kBlock) void sweep_dense_reg(typename Cx<R>::T* __restrict__ psi,
                                                           const Decode<I> dec, const Offs<I, M> off,
-                                                          const UArg<R, M, INL> u) {
+                                                          const UArg<R, M, INL> u,
+                                                          const typename Cx<R>::T* __restrict__ Ug) {
     using T = typename Cx<R>::T;
     const I first = (I)xcd_block() * (I)(kBlock * V) + (I)threadIdx.x;
     I base[V];
@@ -108,21 +86,11 @@ __global__ __launch_bounds__(kBlock) void sweep_dense_reg(typename Cx<R>::T* __r
     for (int v = 0; v < V; ++v)
         if (ok[v]) {
 #pragma unroll
-            for (int r = 0; r < M; ++r) {
-                R yr = 0, yi = 0;
-#pragma unroll
-                for (int a = 0; a < M; ++a) {
-                    const T w = u.get(r * M + a);
-                    yr = fma(w.x, x[v][a].x, yr);
-                    yr = fma(-w.y, x[v][a].y, yr);
-                    yi = fma(w.x, x[v][a].y, yi);
-                    yi = fma(w.y, x[v][a].x, yi);
-                }
-                T y;
-                y.x = yr;
-                y.y = yi;
-                st_stream(psi + base[v] + off.o[r], y);
-            }
+            for (int r = 0; r < M; ++r)
+                st_stream(psi + base[v] + off.o[r], dense_row<R, M>(x[v], [&](int i) {
+                              if constexpr (INL) return u.get(i);
+                              else return Ug[i];
+                          }, r));
         }
 }
 
@@ -159,12 +127,7 @@ __global__ __launch_bounds__(kBlock) void sweep_monomial(typename Cx<R>::T* __re
         if (ok[v]) {
 #pragma unroll
             for (int i = 0; i < A; ++i) {
-                T y = x[v][i];
-                if (!((arg.one_mask >> i) & 1u)) {
-                    const T w = arg.lam[i];
-                    y.x = fma(w.x, x[v][i].x, -w.y * x[v][i].y);
-                    y.y = fma(w.x, x[v][i].y, w.y * x[v][i].x);
-                }
+                const T y = ((arg.one_mask >> i) & 1u) ? x[v][i] : scale_by(arg.lam[i], x[v][i]);
                 st_stream(psi + base[v] + arg.dst[i], y);
             }
         }
@@ -287,12 +250,11 @@ static hipError_t run_dense_reg(const GatePlan& p, void* psi, const double* U, c
             u.u[i].y = static_cast<R>(U[2 * i + 1]);
         }
         hipLaunchKernelGGL((sweep_dense_reg<R, M, I, V, true>), dim3((unsigned)blocks), dim3(kBlock), 0, st,
-                           static_cast<T*>(psi), dec, off, u);
+                           static_cast<T*>(psi), dec, off, u, static_cast<const T*>(nullptr));
     } else {
         UArg<R, M, false> u;
-        u.u = static_cast<const T*>(dgate);
         hipLaunchKernelGGL((sweep_dense_reg<R, M, I, V, false>), dim3((unsigned)blocks), dim3(kBlock), 0, st,
-                           static_cast<T*>(psi), dec, off, u);
+                           static_cast<T*>(psi), dec, off, u, static_cast<const T*>(dgate));
     }
     return hipGetLastError();
 }

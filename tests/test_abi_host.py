@@ -151,3 +151,38 @@ def test_decoder_64bit_path_against_oracle_samples():
             last = qd.class_bases(dims, targets, controls, values, n_cls - 1, 1).astype(np.int64)
             m2, r2 = oracle.class_members(dims, targets, controls, values, last)
             assert r2[0] == 0
+
+
+def test_circuit_plan_partitions_gates_in_order():
+    from qd_inputs import circuits
+    for mk in (circuits.plain, circuits.large):
+        dims, gates = mk()
+        for prec, tile in (("c128", 4096), ("c64", 8192), ("c128", 512)):
+            plan = qd.circuit_plan(dims, gates, prec, tile_amps=tile)
+            assert sum(g for g, _ in plan) == len(gates)
+            assert all(t <= tile for _, t in plan)
+            assert all((t == 0) == (g == 1) for g, t in plan)
+        unfused = qd.circuit_plan(dims, gates, "c128", fuse=False)
+        assert unfused == [(1, 0)] * len(gates)
+    # the whole plain register fits one tile: one pass for the whole circuit
+    dims, gates = circuits.plain()
+    assert qd.circuit_plan(dims, gates, "c128") == [(len(gates), 144)]
+
+
+def test_circuit_plan_skips_identity_and_keeps_big_gates_alone():
+    rng = np.random.default_rng(3)
+    dims = [5, 5, 5, 2, 3]
+    from qd_inputs import Gate
+    gates = [Gate((0,), haar(5, rng)), Gate((1,), np.eye(5)), Gate((0, 1, 2), haar(125, rng)), Gate((3,), shift(2)),
+             Gate((4,), dft(3))]
+    plan = qd.circuit_plan(dims, gates, "c128")
+    assert sum(g for g, _ in plan) == 4          # the identity gate is dropped
+    assert (1, 0) in plan                       # the 125x125 gate runs alone
+
+
+def test_circuit_validation_rejects_bad_gate():
+    from qd_inputs import Gate
+    gates = [Gate((0,), np.eye(2)), Gate((0, 0), np.eye(4))]
+    with pytest.raises(qd.QDError) as e:
+        qd.circuit_plan([2, 2], gates)
+    assert "gate 1" in str(e.value)

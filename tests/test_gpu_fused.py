@@ -1,0 +1,115 @@
+"""LDS-staged fusion (qd_apply_circuit): the fused result must equal the
+one-sweep-per-gate result bit for bit (same per-class arithmetic, gates never
+reordered) and the FP64 oracle within the tolerances."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import assert_close, rand_monomial, rand_state
+from qd_inputs import Gate, circuits, clock, dft, haar, shift, states
+
+pytestmark = pytest.mark.gpu
+
+
+def qd():
+    import paper_2410_17876_amd as q
+    return q
+
+
+def mixed_gates(rng, dims, count, max_m=16):
+    n = len(dims)
+    out = []
+    while len(out) < count:
+        k = int(rng.integers(1, min(3, n) + 1))
+        t = [int(x) for x in rng.choice(n, k, replace=False)]
+        M = math.prod(dims[x] for x in t)
+        if M > max_m:
+            continue
+        rest = [q for q in range(n) if q not in t]
+        m = int(rng.integers(0, min(3, len(rest)) + 1))
+        c = [int(x) for x in rng.choice(rest, m, replace=False)] if m else []
+        v = [int(rng.integers(dims[x])) for x in c]
+        kind = int(rng.integers(5))
+        U = haar(M, rng) if kind < 2 else (rand_monomial(rng, M) if kind == 2 else
+                                           (np.diag(np.exp(2j * np.pi * rng.random(M))) if kind == 3 else
+                                            (np.eye(M) if rng.random() < 0.2 else dft(M))))
+        out.append(Gate(tuple(t), U, tuple(c), tuple(v)))
+    return out
+
+
+CASES = [
+    ([2] * 8 + [3] * 4 + [4, 5], 4096, 64),     # D = 1.66e6
+    ([3, 5, 7, 2, 3, 4, 5, 2, 2], 4096, 64),   # odd radices; low block 105
+    ([2] * 18, 1024, 32),                      # small tiles
+    ([4, 3, 2, 5, 7, 3, 2, 2, 3], 8192, 128),  # big tile
+    ([2, 3, 2, 2, 3, 5], 4096, 64),            # D = 720 <= tile: the whole circuit in one tile
+]
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_fused_equals_sequential_and_oracle(precision, case):
+    dims, tile, run = CASES[case]
+    if precision == "c64":
+        tile *= 2
+    rng = np.random.default_rng(500 + case)
+    D = math.prod(dims)
+    psi0 = rand_state(rng, D)
+    gates = mixed_gates(rng, dims, 60)
+    a = qd().State(dims, precision, init=None).set_amplitudes(psi0)
+    info = a.run_circuit(gates, fuse=True, tile_amps=tile, min_run=run)
+    assert info["fused_passes"] >= 1
+    b = qd().State(dims, precision, init=None).set_amplitudes(psi0)
+    b.run_circuit(gates, fuse=False)
+    c = qd().State(dims, precision, init=None).set_amplitudes(psi0)
+    c.run(gates)
+    ga, gb, gc = a.amplitudes(), b.amplitudes(), c.amplitudes()
+    assert np.array_equal(gb, gc)
+    assert np.array_equal(ga, gc), f"fused differs from sequential: {np.max(np.abs(ga - gc)):.3e}"
+    ref = psi0.copy() if precision == "c128" else (psi0.real.astype(np.float32).astype(np.float64) +
+                                                   1j * psi0.imag.astype(np.float32).astype(np.float64))
+    for g in gates:
+        oracle.apply_gate(dims, ref, g)
+    assert_close(ga, ref, precision, f"fused {dims}")
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_plain_circuit_in_one_launch(precision):
+    dims, gates = circuits.plain()
+    st = qd().State(dims, precision)
+    info = st.run_circuit(gates)
+    assert info == {"passes": 1, "fused_passes": 1}
+    assert_close(st.amplitudes(), oracle.run(dims, gates), precision, "plain circuit, one launch")
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_fused_bit_exact_moves(precision):
+    # permutations inside tiles: X^d on every qudit returns the labelled input bit for bit
+    dims = [3, 2, 5, 4, 2, 7, 3, 2]
+    psi0 = states.labelled(0, math.prod(dims))
+    gates = [Gate((t,), shift(dims[t])) for t in range(len(dims)) for _ in range(dims[t])]
+    st = qd().State(dims, precision, init=None).set_amplitudes(psi0)
+    st.run_circuit(gates, tile_amps=512, min_run=32)
+    assert np.array_equal(st.amplitudes(), psi0)
+
+
+def test_large_tiles_and_errors():
+    q = qd()
+    rng = np.random.default_rng(9)
+    dims = [2] * 16 + [3, 3]
+    gates = mixed_gates(rng, dims, 40)
+    psi0 = rand_state(rng, math.prod(dims))
+    ref = q.State(dims, "c64", init=None).set_amplitudes(psi0)
+    ref.run(gates)
+    big = q.State(dims, "c64", init=None).set_amplitudes(psi0)
+    big.run_circuit(gates, tile_amps=16384, min_run=128)   # 128 KB of LDS per workgroup
+    assert np.array_equal(big.amplitudes(), ref.amplitudes())
+    with pytest.raises(q.QDError):
+        big.run_circuit(gates, tile_amps=65536)
+    bad = list(gates) + [Gate((0, 0), np.eye(4))]
+    before = big.amplitudes()
+    with pytest.raises(q.QDError):
+        big.run_circuit(bad)
+    assert np.array_equal(big.amplitudes(), before)
