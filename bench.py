@@ -44,6 +44,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBPS = 8000.0
+PEAK_MFMA_TFLOPS = {"c64": 157.3, "c128": 78.6}  # dense FP32 / FP64 matrix peaks
 
 
 def log(msg: str) -> None:
@@ -93,7 +94,7 @@ def build_units(qd, dims, gates, precision, mode):
         for g, info in zip(gates, infos):
             if info["kernel"] == "identity":
                 continue
-            units.append((kernel_key(info, precision), info["bytes"], info["updated"], ("gate", g)))
+            units.append((kernel_key(info, precision), info["bytes"], info["updated"], ("gate", g), info["flops"]))
         return units
     plan = qd.circuit_plan(dims, gates, precision, tile_amps=TILE[precision])
     live = [i for i, info in enumerate(infos) if info["kernel"] != "identity"]
@@ -104,10 +105,12 @@ def build_units(qd, dims, gates, precision, mode):
         upd = sum(infos[i]["updated"] for i in idx)
         if tile:
             t = "double" if precision == "c128" else "float"
-            units.append((f"fused_tile<{t}>", 2 * D * ab, upd, ("pass", qd.GateList([gates[i] for i in idx]))))
+            units.append((f"fused_tile<{t}>", 2 * D * ab, upd, ("pass", qd.GateList([gates[i] for i in idx])),
+                          sum(infos[i]["flops"] for i in idx)))
         else:
             i = idx[0]
-            units.append((kernel_key(infos[i], precision), infos[i]["bytes"], upd, ("gate", gates[i])))
+            units.append((kernel_key(infos[i], precision), infos[i]["bytes"], upd, ("gate", gates[i]),
+                          infos[i]["flops"]))
     assert pos == len(live)
     return units
 
@@ -119,7 +122,7 @@ def run_mode(qd, st, dims, gates, precision, mode, steps, warmup):
     stream = st.stream
 
     def step(events=None):
-        for u, (_, _, _, (kind, obj)) in enumerate(units):
+        for u, (_, _, _, (kind, obj), _) in enumerate(units):
             if events is not None:
                 events[u][0].record(stream)
             if kind == "gate":
@@ -145,29 +148,39 @@ def run_mode(qd, st, dims, gates, precision, mode, steps, warmup):
 
     per = {}
     for k in range(steps):
-        for u, (key, nbytes, _, _) in enumerate(units):
-            e = per.setdefault(key, {"launches": 0, "ms": 0.0, "bytes": 0})
+        for u, (key, nbytes, _, _, flops) in enumerate(units):
+            e = per.setdefault(key, {"launches": 0, "ms": 0.0, "bytes": 0, "flops": 0})
             e["launches"] += 1
             e["ms"] += evs[k][u][0].elapsed_time(evs[k][u][1])
             e["bytes"] += nbytes
+            e["flops"] += flops
     updates = steps * sum(u[2] for u in units)
     kernels = {key: {"launches": e["launches"], "avg_us": round(1e3 * e["ms"] / e["launches"], 2),
                      "total_ms": round(e["ms"], 3),
-                     "GBps": round(e["bytes"] / (e["ms"] * 1e-3) / 1e9, 1) if e["ms"] > 0 else None}
+                     "GBps": round(e["bytes"] / (e["ms"] * 1e-3) / 1e9, 1) if e["ms"] > 0 else None,
+                     "TFLOPs": round(e["flops"] / (e["ms"] * 1e-3) / 1e12, 2) if e["ms"] > 0 else None}
                for key, e in per.items()}
     dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
     d = per[dom]
-    achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
-    traffic = load_traffic(dom)
+    if dom.startswith("block_mfma"):
+        achieved = d["flops"] / (d["ms"] * 1e-3) / 1e12
+        peak = PEAK_MFMA_TFLOPS[precision]
+        roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4), "traffic": load_traffic(dom), "kernel": dom,
+                "avg_us": kernels[dom]["avg_us"], "flops_per_launch": d["flops"] // d["launches"],
+                "bytes_per_launch": d["bytes"] // d["launches"]}
+    else:
+        achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": load_traffic(dom), "kernel": dom,
+                "avg_us": kernels[dom]["avg_us"], "bytes_per_launch": d["bytes"] // d["launches"]}
     return {
         "value": updates / wall,
         "ms_per_step": 1e3 * wall / steps,
         "launches_per_step": len(units),
         "updates_per_step": updates // steps,
         "norm_last_step": norms[-1],
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": traffic, "kernel": dom,
-                     "avg_us": kernels[dom]["avg_us"], "bytes_per_launch": d["bytes"] // d["launches"]},
+        "roofline": roof,
         "kernels": kernels,
     }
 
@@ -219,6 +232,7 @@ def main() -> int:
     ap.add_argument("--modes", default="fused,plain", help="comma list of fused, plain")
     ap.add_argument("--no-c64", action="store_true", help="skip the complex64 runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ququint", action="store_true", help="skip the 12-ququint MFMA workload")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--small", action="store_true", help="2^10 x 3^6 x 4^2 register (quick check)")
     ap.add_argument("--tile-c128", type=int, default=0, help="fused tile size, c128 (0 = library default)")
@@ -263,6 +277,14 @@ def main() -> int:
     res = {"c128": run_precision(qd, dims, gates, "c128", upload, args.steps, args.warmup, modes)}
     if not args.no_c64:
         res["c64"] = run_precision(qd, dims, gates, "c64", upload, args.steps, args.warmup, modes)
+    if not args.no_ququint:
+        qdims, qgates = circuits.fused()
+        qst = qd.State(qdims, "c64")
+        log(f"ququint register: D = {qst.D}, {len(qgates)} Haar gates (25x25 and 125x125)")
+        res["ququint"] = run_mode(qd, qst, qdims, qgates, "c64", "plain", args.steps, args.warmup)
+        qst.close()
+        del qst
+        torch.cuda.empty_cache()
     cpu = None
     if host is not None:
         cpu = cpu_baseline(qd, dims, gates, host, args.cpu_seconds)
@@ -289,13 +311,22 @@ def main() -> int:
         "config": {"workload": workload, "D": D, "gates": len(gates), "precision": "c128", "path": head_mode},
         "roofline": h["roofline"],
         "cpu_baseline": cpu,
-        "copy_ceiling_GBps": {p: res[p]["copy_ceiling_GBps"] for p in res},
+        "copy_ceiling_GBps": {p: res[p]["copy_ceiling_GBps"] for p in ("c128", "c64") if p in res},
         "norm_last_step": h["norm_last_step"],
         "launches_per_step": h["launches_per_step"],
         "kernels": h["kernels"],
         "runs": {},
     }
-    for p in res:
+    if "ququint" in res:
+        r = res["ququint"]
+        line["runs"]["ququint_mfma_c64"] = {
+            "workload": "12 ququints (D=5^12), complex64, 300 Haar gates on 2 or 3 qudits (seed 1004), |0..0>",
+            "value": r["value"], "unit": "updates/s", "dtype": "f32", "ms_per_step": r["ms_per_step"],
+            "launches_per_step": r["launches_per_step"], "roofline": r["roofline"],
+            "norm_last_step": r["norm_last_step"], "kernels": r["kernels"]}
+    for p in ("c128", "c64"):
+        if p not in res:
+            continue
         for m in modes:
             if p == "c128" and m == head_mode:
                 continue

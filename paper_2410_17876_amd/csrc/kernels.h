@@ -13,9 +13,17 @@ enum Precision { kC64 = 1, kC128 = 2 };
 inline size_t amp_bytes(int precision) { return precision == kC128 ? 16 : 8; }
 
 // Which kernel family a plan takes.
-enum Family { kFamIdentity = 0, kFamDenseReg = 1, kFamDenseLds = 2, kFamMonomial = 3 };
-int plan_family(const GatePlan& p);
+enum Family { kFamIdentity = 0, kFamDenseReg = 1, kFamDenseLds = 2, kFamMonomial = 3, kFamMfma = 4 };
+int plan_family(const GatePlan& p, int precision);
 const char* family_name(int family);
+
+// Matrix-core path (mfma.hip): dense complex64 gates with 17 <= M <= 128.
+constexpr int kMfmaMinM = 17;
+constexpr int kMfmaMaxM = 128;
+int mfma_padded(int M);
+size_t mfma_gate_bytes(int M, bool narrow);
+void fill_mfma_gate(const GatePlan& p, const double* U, void* dst);
+hipError_t launch_mfma(const GatePlan& p, void* psi, const void* dgate, hipStream_t stream);
 
 // Bytes of device-side gate data (rounded U, member offsets) a plan needs, 0 if
 // everything travels in the kernel arguments.

@@ -1,0 +1,206 @@
+// mfma.hip - dense class updates on the matrix cores (complex64, 17 <= M <= 128).
+//
+// For a gate with a large class (several target qudits, e.g. a 25x25 or 125x125
+// block on ququints) the per-class update y = U x (paper Sec. 2.3) is a dense
+// contraction over all classes at once, Y = U X with X the M x N matrix whose
+// columns are the N classes. With M = 125 that is 8 M = 1000 flops per
+// amplitude, well past the HBM ridge point, so it runs on MFMA:
+//
+//   complex as real:  [Yr; Yi] = [[Ur, -Ui], [Ui, Ur]] [Xr; Xi],
+//
+// a real (2MP x 2MP) by (2MP x N) product with MP = M rounded up to 32, 64 or
+// 128 (padding rows and columns of the real matrix are zero). A workgroup has
+// eight wavefronts; each owns one 32-row block of the real matrix, kept in
+// registers for the whole launch (persistent workgroups loop over column
+// tiles), and one 32-column block of the tile. Per column tile the workgroup
+// gathers the classes' amplitudes into LDS (split into real and imaginary
+// rows), runs v_mfma_f32_32x32x2f32 over K = 2MP, writes the 32x32 result
+// blocks back to LDS and scatters them to the classes' addresses. A tile's
+// classes are read completely before any of them is written, and tiles are
+// disjoint, so the update is in place.
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+#include "kernels.h"
+#include "plan.h"
+
+namespace qd {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kMfmaBlock = 512;  // 8 wavefronts
+
+template <int MP>
+struct MfmaShape {
+    static constexpr int RB = 2 * MP / 32;  // 32-row blocks of the real matrix
+    static constexpr int NB = 8 / RB;       // 32-column blocks per tile
+    static constexpr int NT = 32 * NB;      // columns (classes) per tile
+};
+
+template <int MP, typename I>
+__global__ __launch_bounds__(kMfmaBlock) void block_mfma_c64(typename Cx<float>::T* __restrict__ psi,
+                                                             const Decode<I> dec, const int M, const I ntiles,
+                                                             const float* __restrict__ A,
+                                                             const I* __restrict__ off) {
+    using T = typename Cx<float>::T;
+    using S = MfmaShape<MP>;
+    constexpr int K2 = 2 * MP;
+    constexpr int EPT = MP * S::NT / kMfmaBlock;  // tile elements gathered per thread
+    __shared__ float Bs[K2][S::NT];  // 32 KB: real rows 0..MP-1, imaginary rows MP..2MP-1
+    __shared__ I bases[2][S::NT];    // class bases of the current and the next tile
+    __shared__ I offs[MP];
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int rb = wave % S::RB, cb = wave / S::RB;
+
+    // This wavefront's 32 rows of the real matrix, K = 2MP, two K values per step.
+    float a[MP];
+#pragma unroll
+    for (int s = 0; s < MP; ++s) a[s] = A[(size_t)(32 * rb + (lane & 31)) * K2 + 2 * s + (lane >> 5)];
+    for (int i = threadIdx.x; i < MP; i += kMfmaBlock) offs[i] = i < M ? off[i] : (I)0;
+
+    auto ncols_of = [&](I t) -> int {
+        const I left = dec.n_classes - t * (I)S::NT;
+        return left < (I)S::NT ? (int)left : S::NT;
+    };
+    // Tile t's elements this thread gathers: element e = threadIdx.x + i * block,
+    // row r = e / NT (a class member), column c = e % NT (a class).
+    auto gather = [&](T (&v)[EPT], int buf, int ncols) {
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            const int e = threadIdx.x + i * kMfmaBlock;
+            const int r = e / S::NT, c = e % S::NT;
+            v[i].x = 0.0f;
+            v[i].y = 0.0f;
+            if (r < M && c < ncols) v[i] = ld_stream(psi + bases[buf][c] + offs[r]);
+        }
+    };
+    auto stage = [&](const T (&v)[EPT]) {
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            const int e = threadIdx.x + i * kMfmaBlock;
+            const int r = e / S::NT, c = e % S::NT;
+            Bs[r][c] = v[i].x;
+            Bs[MP + r][c] = v[i].y;
+        }
+    };
+
+    I t = blockIdx.x;
+    int cur = 0;
+    if (t < ntiles) {
+        const int nc = ncols_of(t);
+        if ((int)threadIdx.x < nc) bases[0][threadIdx.x] = decode_base<I>(dec, t * (I)S::NT + (I)threadIdx.x);
+        __syncthreads();
+        T v[EPT];
+        gather(v, 0, nc);
+        stage(v);
+    }
+    for (; t < ntiles; t += gridDim.x) {
+        const int ncols = ncols_of(t);
+        const I tn = t + gridDim.x;
+        const bool has_next = tn < ntiles;
+        const int ncols_next = has_next ? ncols_of(tn) : 0;
+        if ((int)threadIdx.x < ncols_next)
+            bases[cur ^ 1][threadIdx.x] = decode_base<I>(dec, tn * (I)S::NT + (I)threadIdx.x);
+        __syncthreads();  // tile t staged in Bs; next bases visible
+        // Prefetch the next tile into registers; the loads land during this tile's work.
+        T pv[EPT];
+        if (has_next) gather(pv, cur ^ 1, ncols_next);
+        f32x16 acc = {0};
+#pragma unroll
+        for (int s0 = 0; s0 < MP; s0 += 16) {
+            float b[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) b[j] = Bs[2 * (s0 + j) + (lane >> 5)][32 * cb + (lane & 31)];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s0 + j], b[j], acc, 0, 0, 0);
+        }
+        __syncthreads();  // every wavefront has read its B fragments
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            Bs[32 * rb + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)][32 * cb + (lane & 31)] = acc[r];
+        __syncthreads();
+        for (int e = threadIdx.x; e < MP * S::NT; e += kMfmaBlock) {
+            const int r = e / S::NT, c = e % S::NT;
+            if (r < M && c < ncols) {
+                T y;
+                y.x = Bs[r][c];
+                y.y = Bs[MP + r][c];
+                st_stream(psi + bases[cur][c] + offs[r], y);
+            }
+        }
+        __syncthreads();  // Bs free
+        if (has_next) stage(pv);
+        cur ^= 1;
+    }
+}
+
+int mfma_padded(int M) { return M <= 32 ? 32 : (M <= 64 ? 64 : 128); }
+
+size_t mfma_gate_bytes(int M, bool narrow) {
+    const size_t K2 = 2 * (size_t)mfma_padded(M);
+    return K2 * K2 * sizeof(float) + (size_t)M * (narrow ? 4 : 8);
+}
+
+void fill_mfma_gate(const GatePlan& p, const double* U, void* dst) {
+    const int MP = mfma_padded(p.M);
+    const int K2 = 2 * MP;
+    float* A = static_cast<float*>(dst);
+    for (int i = 0; i < K2 * K2; ++i) A[i] = 0.0f;
+    for (int r = 0; r < p.M; ++r)
+        for (int c = 0; c < p.M; ++c) {
+            const float ur = static_cast<float>(U[2 * (r * p.M + c)]);
+            const float ui = static_cast<float>(U[2 * (r * p.M + c) + 1]);
+            A[r * K2 + c] = ur;
+            A[r * K2 + MP + c] = -ui;
+            A[(MP + r) * K2 + c] = ui;
+            A[(MP + r) * K2 + MP + c] = ur;
+        }
+    unsigned char* o = static_cast<unsigned char*>(dst) + (size_t)K2 * K2 * sizeof(float);
+    if (p.D < (1ull << 31)) {
+        uint32_t* oo = reinterpret_cast<uint32_t*>(o);
+        for (int a = 0; a < p.M; ++a) oo[a] = (uint32_t)p.off[a];
+    } else {
+        uint64_t* oo = reinterpret_cast<uint64_t*>(o);
+        for (int a = 0; a < p.M; ++a) oo[a] = (uint64_t)p.off[a];
+    }
+}
+
+template <int MP, typename I>
+static hipError_t run_mfma(const GatePlan& p, void* psi, const void* dgate, hipStream_t st) {
+    using S = MfmaShape<MP>;
+    const Decode<I> dec = make_decode<I>(p);
+    const uint64_t ntiles = (p.n_classes + S::NT - 1) / S::NT;
+    static int per_cu = 0;
+    static int cus = 0;
+    if (!per_cu) {
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, block_mfma_c64<MP, I>, kMfmaBlock, 0);
+        if (e != hipSuccess) return e;
+        if (per_cu < 1) per_cu = 1;
+    }
+    const uint64_t grid = std::min<uint64_t>(ntiles, (uint64_t)per_cu * cus);
+    const float* A = static_cast<const float*>(dgate);
+    const I* off = reinterpret_cast<const I*>(static_cast<const unsigned char*>(dgate) +
+                                              (size_t)(2 * MP) * (2 * MP) * sizeof(float));
+    hipLaunchKernelGGL((block_mfma_c64<MP, I>), dim3((unsigned)grid), dim3(kMfmaBlock), 0, st,
+                       static_cast<typename Cx<float>::T*>(psi), dec, p.M, (I)ntiles, A, off);
+    return hipGetLastError();
+}
+
+hipError_t launch_mfma(const GatePlan& p, void* psi, const void* dgate, hipStream_t st) {
+    if (p.n_classes == 0) return hipSuccess;
+    const bool narrow = p.D < (1ull << 31);
+    switch (mfma_padded(p.M)) {
+        case 32: return narrow ? run_mfma<32, uint32_t>(p, psi, dgate, st) : run_mfma<32, uint64_t>(p, psi, dgate, st);
+        case 64: return narrow ? run_mfma<64, uint32_t>(p, psi, dgate, st) : run_mfma<64, uint64_t>(p, psi, dgate, st);
+        default:
+            return narrow ? run_mfma<128, uint32_t>(p, psi, dgate, st) : run_mfma<128, uint64_t>(p, psi, dgate, st);
+    }
+}
+
+}  // namespace qd

@@ -193,7 +193,7 @@ int plan_gate(const int32_t* dims, int32_t n, const int32_t* targets, int32_t k,
 
 void plan_info(const GatePlan& p, int precision, qd_gate_info* info) {
     std::memset(info, 0, sizeof *info);
-    const int fam = plan_family(p);
+    const int fam = plan_family(p, precision);
     std::snprintf(info->kernel, sizeof info->kernel, "%s", family_name(fam));
     info->category = p.category;
     info->M = p.M;

@@ -178,10 +178,11 @@ __global__ __launch_bounds__(kBlock) void sweep_dense_lds(typename Cx<R>::T* __r
 // ---------------------------------------------------------------------------
 // host side
 
-int plan_family(const GatePlan& p) {
+int plan_family(const GatePlan& p, int precision) {
     if (p.category == kIdentity) return kFamIdentity;
     if ((p.category == kMonomial || p.category == kDiagonal) && p.n_active <= kRegMaxM) return kFamMonomial;
     if (p.M <= kRegMaxM) return kFamDenseReg;
+    if (precision == kC64 && p.category == kDense && p.M >= kMfmaMinM && p.M <= kMfmaMaxM) return kFamMfma;
     return kFamDenseLds;
 }
 
@@ -191,6 +192,7 @@ const char* family_name(int f) {
         case kFamDenseReg: return "sweep_dense_reg";
         case kFamDenseLds: return "sweep_dense_lds";
         case kFamMonomial: return "sweep_monomial";
+        case kFamMfma: return "block_mfma";
     }
     return "?";
 }
@@ -203,7 +205,8 @@ static int lds_classes(int M, int precision) {
 }
 
 size_t device_gate_bytes(const GatePlan& p, int precision) {
-    const int f = plan_family(p);
+    const int f = plan_family(p, precision);
+    if (f == kFamMfma) return mfma_gate_bytes(p.M, use32(p));
     const size_t ab = amp_bytes(precision);
     if (f == kFamDenseReg && p.M > kInlineMaxM) return (size_t)p.M * p.M * ab;
     if (f == kFamDenseLds) return (size_t)p.M * p.M * ab + (size_t)p.M * 8;
@@ -216,7 +219,11 @@ static void round_u(const double* U, int M, R* dst) {
 }
 
 void fill_device_gate(const GatePlan& p, int precision, const double* U, void* dst) {
-    const int f = plan_family(p);
+    const int f = plan_family(p, precision);
+    if (f == kFamMfma) {
+        fill_mfma_gate(p, U, dst);
+        return;
+    }
     if (f != kFamDenseReg && f != kFamDenseLds) return;
     if (precision == kC128)
         round_u<double>(U, p.M, static_cast<double*>(dst));
@@ -319,8 +326,9 @@ static hipError_t dispatch_monomial(const GatePlan& p, void* psi, hipStream_t st
 template <typename R, typename I>
 static hipError_t launch_typed(const GatePlan& p, int precision, void* psi, const double* U,
                                const void* dgate, hipStream_t st) {
-    switch (plan_family(p)) {
+    switch (plan_family(p, precision)) {
         case kFamIdentity: return hipSuccess;
+        case kFamMfma: return launch_mfma(p, psi, dgate, st);
         case kFamMonomial: return dispatch_monomial<R, I>(p, psi, st);
         case kFamDenseReg: return dispatch_dense_reg<R, I>(p, psi, U, dgate, st);
         case kFamDenseLds: return run_dense_lds<R, I>(p, precision, psi, dgate, st);

@@ -102,6 +102,9 @@ def test_gate_categories_from_zero_pattern():
     h = qd.gate_info(dims, [0, 2], haar(10, rng))
     assert h["kernel"] == "sweep_dense_reg" and h["flops"] == 8 * 30 * 10
     assert qd.gate_info([5, 5, 5, 2], [0, 1, 2], haar(125, rng))["kernel"] == "sweep_dense_lds"
+    assert qd.gate_info([5, 5, 5, 2], [0, 1, 2], haar(125, rng), precision="c64")["kernel"] == "block_mfma"
+    assert qd.gate_info([5, 5, 2], [0, 1], haar(25, rng), precision="c64")["kernel"] == "block_mfma"
+    assert qd.gate_info([7, 7, 7], [0, 1, 2], haar(343, rng), precision="c64")["kernel"] == "sweep_dense_lds"
 
 
 def _rand_case(rng):

@@ -1,0 +1,140 @@
+"""Matrix-core path (complex64 dense gates with 17 <= M <= 128) against the FP64
+oracle, and the ququint workload: 2- and 3-qudit Haar gates (25x25, 125x125).
+
+Tolerance: complex64, max-abs <= 2e-5 and <= 1e-5 of the largest amplitude,
+per gate layer (a layer = one gate, as each gate is one launch here)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import assert_close, gpu_values, rand_state, upload_chunks
+from qd_inputs import Gate, circuits, haar, states
+
+pytestmark = pytest.mark.gpu
+
+
+def qd():
+    import paper_2410_17876_amd as q
+    return q
+
+
+def round32(v):
+    return v.real.astype(np.float32).astype(np.float64) + 1j * v.imag.astype(np.float32).astype(np.float64)
+
+
+CASES = [  # (dims, targets): M = 18, 25, 27, 36, 48, 49, 64, 100, 125, 126
+    ([2, 3, 3, 2, 5, 2, 3], [1, 2, 0]),
+    ([5, 2, 5, 3, 2, 2, 3], [0, 2]),
+    ([3, 3, 2, 3, 5, 2, 2], [0, 1, 3]),
+    ([6, 2, 6, 3, 2, 5], [2, 0]),
+    ([4, 3, 2, 4, 5, 2], [3, 1, 0]),
+    ([7, 3, 7, 2, 2, 3], [2, 0]),
+    ([4, 4, 4, 3, 2, 5], [0, 1, 2]),
+    ([5, 3, 5, 4, 2, 3], [2, 3, 0]),
+    ([5, 5, 5, 3, 2, 2, 2], [0, 1, 2]),
+    ([2, 7, 6, 3, 3, 2], [1, 2, 3]),
+]
+
+
+@pytest.mark.parametrize("dims,targets", CASES)
+def test_mfma_gate_vs_oracle(dims, targets):
+    rng = np.random.default_rng(sum(dims) * 7 + len(targets))
+    D = math.prod(dims)
+    M = math.prod(dims[t] for t in targets)
+    assert qd().gate_info(dims, targets, haar(M, rng), precision="c64")["kernel"] == "block_mfma"
+    psi0 = rand_state(rng, D)
+    U = haar(M, rng)
+    rest = [q for q in range(len(dims)) if q not in targets]
+    for controls, values in (((), ()), ((rest[-1],), (dims[rest[-1]] - 1,))):
+        st = qd().State(dims, "c64", init=None).set_amplitudes(psi0)
+        st.apply(targets, U, controls, values)
+        ref = oracle.apply(dims, round32(psi0), targets, U, controls, values)
+        assert_close(st.amplitudes(), ref, "c64", f"M={M} controls={controls}")
+
+
+def test_mfma_roundtrip_and_determinism():
+    rng = np.random.default_rng(3)
+    dims = [5, 5, 5, 5, 3, 2]
+    psi0 = rand_state(rng, math.prod(dims))
+    gates = [Gate(tuple(int(x) for x in rng.choice(4, 3, replace=False)), haar(125, rng)) for _ in range(6)]
+    gates += [Gate(tuple(int(x) for x in rng.choice(4, 2, replace=False)), haar(25, rng)) for _ in range(6)]
+    a = qd().State(dims, "c64", init=None).set_amplitudes(psi0).run(gates)
+    b = qd().State(dims, "c64", init=None).set_amplitudes(psi0).run(gates)
+    assert np.array_equal(a.amplitudes(), b.amplitudes())
+    for g in reversed(gates):
+        a.apply_gate(g.inverse())
+    assert_close(a.amplitudes(), round32(psi0), "c64", "roundtrip")
+
+
+def test_ququint_circuit_per_layer_vs_oracle():
+    # The ququint workload's gate mix on 8 ququints (D = 390625), GPU and oracle
+    # advanced in lockstep from |0..0>; the error is recorded after every layer.
+    dims, gates = circuits.fused(dims=[5] * 8, n_gates=60)
+    st = qd().State(dims, "c64")
+    ref = oracle.zero_state(dims)
+    errs = []
+    for g in gates:
+        st.apply_gate(g)
+        oracle.apply_gate(dims, ref, g)
+        got = st.amplitudes()
+        errs.append(float(np.max(np.abs(got - ref))))
+        assert_close(got, ref, "c64", f"layer {len(errs) - 1} ({g.kind} on {g.targets})")
+    print(f"[ququint 5^8] per-layer max-abs error: first {errs[0]:.2e}, last {errs[-1]:.2e}, max {max(errs):.2e}")
+
+
+def test_64bit_path_mfma():
+    # D >= 2^31 (5^14 = 6.1e9 would be 49 GB in c64; 5^13 x 2 = 2.4e9 suffices).
+    import torch
+
+    dims = [5] * 13 + [2]
+    D = math.prod(dims)
+    assert D >= 2**31
+    st = qd().State(dims, "c64", init=None)
+    upload_chunks(st, lambda s, c: states.labelled(s, c), chunk=1 << 24)
+    rng = np.random.default_rng(11)
+    idx = np.concatenate([rng.integers(0, D, size=3000), [0, D - 1]])
+    for targets in ((12, 3, 7), (0, 13)):
+        M = math.prod(dims[t] for t in targets)
+        g = Gate(targets, haar(M, rng))
+        st.apply_gate(g)
+        want = oracle.apply_sampled(dims, g, idx, states.labelled_at)
+        got = gpu_values(st, idx)
+        assert np.max(np.abs(got - want)) <= 1e-5 * np.max(np.abs(want)), targets
+        st.apply_gate(g.inverse())
+    st.close()
+    del st
+    torch.cuda.empty_cache()
+
+
+def test_full_ququint_register_sampled():
+    # The full workload register: 12 ququints (D = 2.44e8). Single gates of the
+    # workload on a seeded Gaussian input, sampled outputs vs the oracle's sampled
+    # form (inputs straight from the generator), then the 300-gate circuit and its
+    # inverse return the input.
+    import torch
+
+    dims, gates = circuits.fused()
+    D = math.prod(dims)
+    G = states.GaussianState(D, seed=77)
+    G.cache_chunks = 240
+    st = qd().State(dims, "c64", init=None)
+    G.fill(lambda start, vals: st.set_interleaved(vals, start))
+    rng = np.random.default_rng(5)
+    idx = np.concatenate([rng.integers(0, D, size=2000), [0, D - 1]])
+    inp = lambda ix: round32(G.values(ix))
+    for g in gates[:8]:
+        st.apply_gate(g)
+        assert_close(gpu_values(st, idx), oracle.apply_sampled(dims, g, idx, inp), "c64", f"{g.kind} {g.targets}")
+        st.apply_gate(g.inverse())
+    st.run(gates)
+    assert abs(st.norm() - 1.0) < 1e-4
+    for g in reversed(gates):
+        st.apply_gate(g.inverse())
+    err = float(np.max(np.abs(gpu_values(st, idx) - inp(idx))))
+    print(f"[ququint 5^12] 600-gate roundtrip max-abs error {err:.3e}")
+    assert err <= 2e-5
+    st.close()
+    del st
+    torch.cuda.empty_cache()
