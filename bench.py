@@ -206,6 +206,60 @@ def run_precision(qd, dims, gates, precision, upload, steps, warmup, modes):
     return out
 
 
+def run_batched(qd, precision, steps, warmup, tune_cache):
+    """The batched workload: 512 independent circuits (6..16 qudits, d in 2..5,
+    D <= 1e6, depth 100..1000, |0..0>) advanced together by qd_batch_apply."""
+    import torch
+    from qd_inputs import circuits
+
+    specs = circuits.batched_specs()
+    t0 = time.time()
+    lists = [qd.GateList(s.gates()) for s in specs]
+    log(f"batched {precision}: {len(specs)} circuits generated in {time.time() - t0:.1f} s "
+        f"(sum D = {sum(s.D for s in specs)}, gates = {sum(len(g) for g in lists)})")
+    # Autotune the tile shape on a sample: 64 circuits, first 100 gates each.
+    sample = qd.batch.BatchRunner([s.dims for s in specs[:64]], precision)
+    sample_lists = [qd.GateList(g.gates[:100]) for g in lists[:64]]
+
+    def trial(tile, run_len):
+        sample.run(sample_lists, tile_amps=tile, min_run=run_len)
+
+    tuned = qd.tune.tune(trial, precision, "batched-workload-v1", tune_cache)
+    sample.close()
+    tile, run_len = tuned["tile_amps"], tuned["min_run"]
+    log(f"batched {precision}: autotuned tile {tile}, min run {run_len} ({'cached' if tuned['cached'] else 'measured'})")
+    runner = qd.batch.BatchRunner([s.dims for s in specs], precision)
+    ab = 16 if precision == "c128" else 8
+    updates = 0
+    pass_bytes = 0
+    for s, gl in zip(specs, lists):
+        infos = [qd.gate_info(s.dims, g.targets, g.U, g.controls, g.values, precision) for g in gl.gates]
+        updates += sum(i["updated"] for i in infos)
+        npass = len(qd.circuit_plan(s.dims, gl, precision, tile_amps=tile, min_run=run_len))
+        pass_bytes += npass * 2 * s.D * ab
+    for w in range(warmup):
+        info = runner.run(lists, tile_amps=tile, min_run=run_len)
+        log(f"batched {precision}: warmup {w}: {info['rounds']} rounds, {info['items']} items, {info['seconds']:.3f} s")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        info = runner.run(lists, tile_amps=tile, min_run=run_len)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    norms = [st.norm() for st in runner.states[:8]]
+    runner.close()
+    torch.cuda.empty_cache()
+    log(f"batched {precision}: {steps} timed steps in {wall:.3f} s; norms of the first states {norms[:3]}")
+    achieved = pass_bytes * steps / wall / 1e9
+    return {"value": updates * steps / wall, "unit": "updates/s", "dtype": "f64" if precision == "c128" else "f32",
+            "ms_per_step": 1e3 * wall / steps, "launch_rounds_per_step": info["rounds"],
+            "items_per_step": info["items"], "autotuned": {"tile_amps": tile, "min_run": run_len,
+                                                           "timings_s": tuned.get("timings_s")},
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                         "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": None, "kernel": "batch_tile",
+                         "note": "whole-run average over all rounds: 2 x D x bytes per (state, pass)"}}
+
+
 def cpu_baseline(qd, dims, gates, psi, seconds):
     import oracle
 
@@ -233,6 +287,9 @@ def main() -> int:
     ap.add_argument("--no-c64", action="store_true", help="skip the complex64 runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ququint", action="store_true", help="skip the 12-ququint MFMA workload")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 512-circuit batched workload")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "tune_cache.json"),
+                    help="autotuner cache file")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--small", action="store_true", help="2^10 x 3^6 x 4^2 register (quick check)")
     ap.add_argument("--tile-c128", type=int, default=0, help="fused tile size, c128 (0 = library default)")
@@ -285,6 +342,9 @@ def main() -> int:
         qst.close()
         del qst
         torch.cuda.empty_cache()
+    if not args.no_batched:
+        for p in (["c64", "c128"] if not args.no_c64 else ["c128"]):
+            res[f"batched_{p}"] = run_batched(qd, p, args.steps, args.warmup, args.tune_cache)
     cpu = None
     if host is not None:
         cpu = cpu_baseline(qd, dims, gates, host, args.cpu_seconds)
@@ -324,6 +384,11 @@ def main() -> int:
             "value": r["value"], "unit": "updates/s", "dtype": "f32", "ms_per_step": r["ms_per_step"],
             "launches_per_step": r["launches_per_step"], "roofline": r["roofline"],
             "norm_last_step": r["norm_last_step"], "kernels": r["kernels"]}
+    for p in ("c64", "c128"):
+        if f"batched_{p}" in res:
+            line["runs"][f"batched_{p}"] = dict(
+                res[f"batched_{p}"],
+                workload="512 circuits, 6..16 qudits, d in 2..5, D <= 1e6, depth 100..1000 (seed 1002), |0..0>")
     for p in ("c128", "c64"):
         if p not in res:
             continue

@@ -192,6 +192,30 @@ int qd_apply_circuit(qd_state* s, const qd_gate_desc* gates, int32_t count, qd_c
 int qd_circuit_plan(const int32_t* dims, int32_t n, int32_t precision, const qd_gate_desc* gates, int32_t count,
                     const qd_circuit_options* opts, int32_t* pass_gates, int32_t* pass_tile, int32_t* npasses);
 
+/* ---- batches of independent states ---------------------------------------------- */
+
+/* A batch context holds the staging buffers of qd_batch_apply for one precision.
+ * It may be reused for any number of calls; one context must not be used from
+ * two threads at once. */
+typedef struct qd_batch qd_batch;
+int qd_batch_create(int32_t precision, qd_batch** out);
+int qd_batch_destroy(qd_batch* b);
+
+/* Apply gate list i (gates[i][0..counts[i]-1]) to states[i] for every i, in
+ * order per state, advancing all states together: each state's list is split
+ * into fused passes as in qd_apply_circuit, and round r is ONE launch that runs
+ * pass r of every state still having one (a workgroup per (state, tile)). A
+ * state whose whole register fits one tile runs its whole list in one round.
+ * The result of every state is bitwise the same as running its list alone
+ * through qd_apply_circuit with the same options. All states must have the
+ * batch's precision, fewer than 2^31 amplitudes, and one device and stream
+ * (the launches go to that stream); a state may appear once. Everything is
+ * validated before any work is enqueued. opts (may be null) gives the tile
+ * options; on return opts->passes = rounds launched, opts->fused_passes =
+ * (state, pass) items run. */
+int qd_batch_apply(qd_batch* b, qd_state* const* states, const qd_gate_desc* const* gates, const int32_t* counts,
+                   int32_t nstates, qd_circuit_options* opts);
+
 /* ||psi||_2 = sqrt(sum_j |a_j|^2), summed in FP64 on the device in a fixed
  * order (the same result for the same state, run after run). Synchronous. */
 int qd_norm(const qd_state* s, double* out);

@@ -75,6 +75,10 @@ def _load() -> C.CDLL:
         "qd_apply_circuit": [vp, C.POINTER(GateDesc), C.c_int32, C.POINTER(CircuitOptions)],
         "qd_circuit_plan": [i32p, C.c_int32, C.c_int32, C.POINTER(GateDesc), C.c_int32, C.POINTER(CircuitOptions),
                             i32p, i32p, i32p],
+        "qd_batch_create": [C.c_int32, C.POINTER(vp)],
+        "qd_batch_destroy": [vp],
+        "qd_batch_apply": [vp, C.POINTER(vp), C.POINTER(C.POINTER(GateDesc)), i32p, C.c_int32,
+                           C.POINTER(CircuitOptions)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -304,3 +308,37 @@ class State:
             self.close()
         except Exception:
             pass
+
+
+class Batch:
+    """A batch context (qd_batch): advances many independent states together."""
+
+    def __init__(self, precision="c128"):
+        self.precision = PRECISIONS[precision]
+        self._h = C.c_void_p()
+        check(lib.qd_batch_create(self.precision, C.byref(self._h)))
+
+    def apply(self, states, gate_lists, tile_amps=0, min_run=0) -> dict:
+        """Apply gate_lists[i] to states[i] for all i (qd_batch_apply)."""
+        n = len(states)
+        if len(gate_lists) != n:
+            raise ValueError("one gate list per state")
+        gls = [g if isinstance(g, GateList) else GateList(g) for g in gate_lists]
+        hs = (C.c_void_p * max(1, n))(*[st.handle for st in states])
+        gp = (C.POINTER(GateDesc) * max(1, n))(*[C.cast(g.descs, C.POINTER(GateDesc)) for g in gls])
+        counts = np.array([len(g) for g in gls] or [0], dtype=np.int32)
+        opts = _options(True, tile_amps, min_run)
+        check(lib.qd_batch_apply(self._h, hs, gp, counts.ctypes.data_as(C.POINTER(C.c_int32)), n, C.byref(opts)))
+        return {"rounds": opts.passes, "items": opts.fused_passes}
+
+    def close(self) -> None:
+        if self._h:
+            lib.qd_batch_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+

@@ -477,6 +477,222 @@ int qd_apply_circuit(qd_state* s, const qd_gate_desc* gates, int32_t count, qd_c
     return QD_OK;
 }
 
+}  // extern "C"
+
+// A batch context: staging for the per-round descriptor blobs of qd_batch_apply.
+// Two pinned host buffers and two device buffers alternate between rounds; a
+// host buffer is refilled only after its previous copy has finished (event),
+// a device buffer only after the kernel that read it (stream order).
+struct qd_batch {
+    int precision = 0;
+    struct Buf {
+        unsigned char* host = nullptr;
+        unsigned char* dev = nullptr;
+        size_t cap = 0;
+        hipEvent_t ev = nullptr;
+        bool pending = false;
+    } buf[2];
+    int next = 0;
+};
+
+namespace {
+
+void batch_free(qd_batch* b) {
+    for (auto& x : b->buf) {
+        if (x.ev) (void)hipEventSynchronize(x.ev), (void)hipEventDestroy(x.ev);
+        if (x.dev) (void)hipFree(x.dev);
+        if (x.host) (void)hipHostFree(x.host);
+        x = qd_batch::Buf();
+    }
+}
+
+// Stage `bytes` into the next buffer pair and copy it to the device on `st`.
+int batch_stage(qd_batch* b, const std::vector<unsigned char>& data, hipStream_t st, const unsigned char** dptr) {
+    qd_batch::Buf& x = b->buf[b->next];
+    b->next ^= 1;
+    if (x.pending) QD_HIP(hipEventSynchronize(x.ev), "batch staging");
+    if (data.size() > x.cap) {
+        QD_HIP(hipStreamSynchronize(st), "batch staging");  // the old device buffer may still be read
+        if (x.dev) (void)hipFree(x.dev);
+        if (x.host) (void)hipHostFree(x.host);
+        x.dev = nullptr;
+        x.host = nullptr;
+        size_t cap = std::max<size_t>(data.size(), 1u << 20);
+        cap += cap / 2;
+        if (hipHostMalloc(reinterpret_cast<void**>(&x.host), cap, hipHostMallocDefault) != hipSuccess) {
+            x.host = nullptr;
+            x.cap = 0;
+            return set_err(QD_ERR_OUT_OF_MEMORY, "pinned batch staging allocation failed");
+        }
+        if (hipMalloc(reinterpret_cast<void**>(&x.dev), cap) != hipSuccess) {
+            (void)hipHostFree(x.host);
+            x.host = nullptr;
+            x.dev = nullptr;
+            x.cap = 0;
+            return set_err(QD_ERR_OUT_OF_MEMORY, "device batch buffer allocation failed");
+        }
+        x.cap = cap;
+        if (!x.ev) QD_HIP(hipEventCreateWithFlags(&x.ev, hipEventDisableTiming), "event");
+    }
+    std::memcpy(x.host, data.data(), data.size());
+    QD_HIP(hipMemcpyAsync(x.dev, x.host, data.size(), hipMemcpyHostToDevice, st), "batch upload");
+    QD_HIP(hipEventRecord(x.ev, st), "batch staging");
+    x.pending = true;
+    *dptr = x.dev;
+    return QD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int qd_batch_create(int32_t precision, qd_batch** out) {
+    if (!out) return set_err(QD_ERR_INVALID_ARGUMENT, "out is null");
+    *out = nullptr;
+    int rc = check_precision(precision);
+    if (rc) return rc;
+    qd_batch* b = new qd_batch();
+    b->precision = precision;
+    *out = b;
+    return QD_OK;
+}
+
+int qd_batch_destroy(qd_batch* b) {
+    if (!b) return QD_OK;
+    batch_free(b);
+    delete b;
+    return QD_OK;
+}
+
+int qd_batch_apply(qd_batch* b, qd_state* const* states, const qd_gate_desc* const* gates, const int32_t* counts,
+                   int32_t nstates, qd_circuit_options* opts) {
+    if (!b) return set_err(QD_ERR_INVALID_ARGUMENT, "batch is null");
+    if (nstates < 0) return set_err(QD_ERR_INVALID_ARGUMENT, "negative state count");
+    if (nstates == 0) return QD_OK;
+    if (!states || !gates || !counts) return set_err(QD_ERR_INVALID_ARGUMENT, "states, gates or counts is null");
+    // Validate everything before enqueuing anything.
+    std::vector<std::vector<CircuitGate>> cg(nstates);
+    for (int i = 0; i < nstates; ++i) {
+        const qd_state* s = states[i];
+        if (!s) return set_err(QD_ERR_INVALID_ARGUMENT, "state " + std::to_string(i) + " is null");
+        if (s->precision != b->precision)
+            return set_err(QD_ERR_INVALID_ARGUMENT, "state " + std::to_string(i) + " has another precision");
+        if (s->device != states[0]->device || s->stream != states[0]->stream)
+            return set_err(QD_ERR_INVALID_ARGUMENT, "all states of a batch must share one device and stream");
+        if (s->D >= (1ull << 31))
+            return set_err(QD_ERR_NOT_SUPPORTED, "batched states must have fewer than 2^31 amplitudes");
+        for (int j = 0; j < i; ++j)
+            if (states[j] == s) return set_err(QD_ERR_INVALID_ARGUMENT, "a state appears twice in a batch");
+        int rc = circuit_gates(s->dims, s->n, gates[i], counts[i], cg[i]);
+        if (rc) return set_err(rc, "state " + std::to_string(i) + ": " + qd_last_error());
+    }
+    CircuitOptions co;
+    int rc = circuit_options(opts, b->precision, &co);
+    if (rc) return rc;
+    co.fuse = true;
+    co.tables = false;
+    co.single_as_fused = true;
+    std::vector<std::vector<PassPlan>> plans(nstates);
+    size_t rounds = 0;
+    for (int i = 0; i < nstates; ++i) {
+        std::string err;
+        rc = plan_circuit(states[i]->dims, states[i]->n, b->precision, cg[i].data(), counts[i], co, plans[i], &err);
+        if (rc) return set_err(rc, "state " + std::to_string(i) + ": " + err);
+        rounds = std::max(rounds, plans[i].size());
+    }
+    qd_state* s0 = states[0];
+    rc = use_device(s0);
+    if (rc) return rc;
+    hipStream_t st = s0->stream;
+    int32_t items_total = 0;
+    GatePlan p;
+    for (size_t r = 0; r < rounds; ++r) {
+        // Round r: pass r of every state that has one; fused passes go into one
+        // launch, any one-gate sweep (a gate too large for a tile) runs after it.
+        std::vector<BatchItem> items;
+        std::vector<unsigned char> blob;
+        std::vector<int> singles;
+        uint64_t nblocks = 0;
+        uint32_t max_tile = 0;
+        for (int i = 0; i < nstates; ++i) {
+            if (r >= plans[i].size()) continue;
+            const PassPlan& pp = plans[i][r];
+            if (!pp.fused || pp.launch.outer_nseg > kTileMaxSeg) {
+                singles.push_back(i);
+                continue;
+            }
+            if (pp.launch.ngates == 0) continue;
+            const FusedLaunch& f = pp.launch;
+            const size_t base = (blob.size() + 15) / 16 * 16;
+            blob.resize(base + pp.blob.size());
+            std::memcpy(blob.data() + base, pp.blob.data(), pp.blob.size());
+            TileGate* tg = reinterpret_cast<TileGate*>(blob.data() + base + f.gates_off);
+            for (int g = 0; g < f.ngates; ++g) {
+                tg[g].u_off += (uint32_t)base;
+                if (tg[g].bases_off != kDecodeBases) tg[g].bases_off += (uint32_t)base;
+            }
+            BatchItem it;
+            std::memset(&it, 0, sizeof it);
+            it.psi = reinterpret_cast<uint64_t>(states[i]->psi);
+            it.outer.n_classes = (uint32_t)f.n_tiles;
+            it.outer.ctrl_off = 0;
+            it.outer.nseg = f.outer_nseg;
+            for (int g = 0; g < kTileMaxSeg; ++g) {
+                it.outer.size[g] = g < f.outer_nseg ? (uint32_t)f.outer_size[g] : 1u;
+                it.outer.stride[g] = g < f.outer_nseg ? (uint32_t)f.outer_stride[g] : 0u;
+                it.outer.div[g] = make_fast_div<uint32_t>(g < f.outer_nseg ? f.outer_size[g] : 1);
+            }
+            it.tile = f.tile;
+            it.L = f.L;
+            it.chunks_per_run = (f.L + 63) / 64;
+            it.nchunks = (f.tile / f.L) * it.chunks_per_run;
+            it.cdiv = make_fast_div<uint32_t>(it.chunks_per_run);
+            it.ngates = f.ngates;
+            it.gates_off = (uint32_t)(base + f.gates_off);
+            it.run_off_off = (uint32_t)(base + f.run_off_off);
+            it.first_block = (uint32_t)nblocks;
+            nblocks += f.n_tiles;
+            max_tile = std::max(max_tile, f.tile);
+            items.push_back(it);
+        }
+        if (nblocks >= 0x7fffffffull) return set_err(QD_ERR_NOT_SUPPORTED, "batched round too large");
+        if (!items.empty()) {
+            const size_t items_off = (blob.size() + 15) / 16 * 16;
+            blob.resize(items_off + items.size() * sizeof(BatchItem));
+            std::memcpy(blob.data() + items_off, items.data(), items.size() * sizeof(BatchItem));
+            const unsigned char* dblob = nullptr;
+            rc = batch_stage(b, blob, st, &dblob);
+            if (rc) return rc;
+            QD_HIP(launch_batch(b->precision, dblob + items_off, (int)items.size(), (uint32_t)nblocks, max_tile, dblob,
+                                st),
+                   "batch launch");
+            items_total += (int32_t)items.size();
+        }
+        for (int i : singles) {
+            const PassPlan& pp = plans[i][r];
+            qd_state* s = states[i];
+            if (pp.fused) {  // a fused pass whose outer decode does not fit a batch item
+                const void* dblob = nullptr;
+                rc = stage(s, pp.blob.data(), pp.blob.size(), &dblob);
+                if (rc) return rc;
+                QD_HIP(launch_fused(pp.launch, s->precision, s->psi, dblob, s->stream), "fused launch");
+                continue;
+            }
+            const CircuitGate& g = cg[i][pp.gates[0]];
+            std::string err;
+            rc = plan_gate(s->dims, s->n, g.targets, g.k, g.controls, g.values, g.m, g.U, &p, &err);
+            if (rc) return set_err(rc, err);
+            rc = enqueue_single(s, p, g.U);
+            if (rc) return rc;
+        }
+    }
+    if (opts) {
+        opts->passes = (int32_t)rounds;
+        opts->fused_passes = items_total;
+    }
+    return QD_OK;
+}
+
 int qd_norm(const qd_state* s, double* out) {
     if (!s || !out) return set_err(QD_ERR_INVALID_ARGUMENT, "state or out is null");
     int rc = use_device(s);

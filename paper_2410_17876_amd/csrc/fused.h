@@ -29,14 +29,18 @@ constexpr int kFuseMaxGates = 64;   // gates per fused pass
 constexpr int kMaxOuterCtl = 8;     // controls outside S per gate
 constexpr int kFuseBlock = 256;
 
-// A gate's classes inside a tile are the same for every tile, so their tile-local
-// bases are computed once on the host (uint16: a tile has at most 32768
-// amplitudes) instead of being decoded per class and per tile on the device.
+// A gate's classes inside a tile are the same for every tile. A single-state
+// pass ships their tile-local bases as a uint16 table (a tile has at most 32768
+// amplitudes); a batched pass, whose descriptors are uploaded every round,
+// decodes them on the device instead (bases_off == kDecodeBases).
+constexpr uint32_t kDecodeBases = 0xffffffffu;
+
 struct TileGate {
     int32_t kind;        // kDense, or kMonomial for monomial and diagonal gates
     int32_t M;           // dense: class size; monomial: number of active entries
     uint32_t n_classes;                 // classes of the gate inside one tile
-    uint32_t bases_off;                 // byte offset of the uint16 class bases in the blob
+    uint32_t bases_off;                 // byte offset of the uint16 class bases in the blob, or kDecodeBases
+    Decode<uint32_t, kTileMaxSeg> dec;  // tile-local class decoder
     uint32_t off[kFuseMaxM];            // dense: member offsets; monomial: source offsets
     uint32_t dst[kFuseMaxM];            // monomial: destination offsets
     uint32_t one_mask;                  // monomial: bit i set if factor i is exactly 1
@@ -59,6 +63,19 @@ struct FusedArgs {
     uint32_t nchunks;                   // runs * chunks_per_run
     FastDiv<uint32_t> cdiv;             // division by chunks_per_run
     int32_t ngates;
+};
+
+// One (state, fused pass) of a batched round. Workgroups [first_block,
+// first_block + n_tiles) of the launch process this item's tiles.
+struct BatchItem {
+    uint64_t psi;                        // device address of the state's amplitudes
+    Decode<uint32_t, kTileMaxSeg> outer; // tile id -> tile base
+    uint32_t tile, L, chunks_per_run, nchunks;
+    FastDiv<uint32_t> cdiv;
+    int32_t ngates;
+    uint32_t gates_off;                  // byte offsets into the round's blob
+    uint32_t run_off_off;
+    uint32_t first_block;
 };
 
 }  // namespace qd

@@ -40,7 +40,7 @@ __device__ __forceinline__ void tile_dense(typename Cx<R>::T* tile, const TileGa
 #pragma unroll
         for (int u = 0; u < UF; ++u) {
             ok[u] = c0 + u * kFuseBlock < nc;
-            base[u] = ok[u] ? bases[c0 + u * kFuseBlock] : 0u;
+            base[u] = !ok[u] ? 0u : (bases ? bases[c0 + u * kFuseBlock] : decode_base<uint32_t>(G->dec, c0 + u * kFuseBlock));
         }
         T x[UF][M];
 #pragma unroll
@@ -86,7 +86,7 @@ __device__ __forceinline__ void tile_mono(typename Cx<R>::T* tile, const TileGat
 #pragma unroll
         for (int u = 0; u < UF; ++u) {
             ok[u] = c0 + u * kFuseBlock < nc;
-            base[u] = ok[u] ? bases[c0 + u * kFuseBlock] : 0u;
+            base[u] = !ok[u] ? 0u : (bases ? bases[c0 + u * kFuseBlock] : decode_base<uint32_t>(G->dec, c0 + u * kFuseBlock));
         }
         T x[UF][A];
 #pragma unroll
@@ -104,11 +104,17 @@ __device__ __forceinline__ void tile_mono(typename Cx<R>::T* tile, const TileGat
     }
 }
 
-// Tile <-> HBM: a tile is `runs` contiguous runs of L amplitudes. Each wavefront
-// takes 64-amplitude chunks of runs; the run (and its offset) is uniform per
-// wavefront, so the only per-lane work is one add.
+// Geometry of one tile: `nchunks` wavefront-sized chunks of `runs` contiguous
+// runs of L amplitudes each.
+struct TileGeom {
+    uint32_t tile, L, chunks_per_run, nchunks;
+    FastDiv<uint32_t> cdiv;
+};
+
+// Tile <-> HBM. Each wavefront takes 64-amplitude chunks of runs; the run (and
+// its offset) is uniform per wavefront, so the only per-lane work is one add.
 template <typename T, typename I, bool LOAD>
-__device__ __forceinline__ void move_tile(T* __restrict__ psi, T* tile, I obase, const FusedArgs<I>& a,
+__device__ __forceinline__ void move_tile(T* __restrict__ psi, T* tile, I obase, const TileGeom& a,
                                           const I* __restrict__ run_off) {
     constexpr uint32_t nw = kFuseBlock / 64;
     constexpr int U4 = 4;
@@ -143,23 +149,22 @@ __device__ __forceinline__ void move_tile(T* __restrict__ psi, T* tile, I obase,
     }
 }
 
+// One tile of one fused pass: load, apply the pass's gates in order, store.
 template <typename R, typename I>
-__global__ __launch_bounds__(kFuseBlock) void fused_tile(typename Cx<R>::T* __restrict__ psi, const FusedArgs<I> a,
-                                                         const TileGate* __restrict__ gates,
-                                                         const unsigned char* __restrict__ blob,
-                                                         const I* __restrict__ run_off) {
+__device__ __forceinline__ void process_tile(typename Cx<R>::T* __restrict__ psi, typename Cx<R>::T* tile, I obase,
+                                             const TileGeom& geo, int ngates, const TileGate* __restrict__ gates,
+                                             const unsigned char* __restrict__ blob,
+                                             const I* __restrict__ run_off) {
     using T = typename Cx<R>::T;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* tile = reinterpret_cast<T*>(smem_raw);
-    const I obase = decode_base<I>(a.outer, (I)xcd_block());
-    move_tile<T, I, true>(psi, tile, obase, a, run_off);
+    move_tile<T, I, true>(psi, tile, obase, geo, run_off);
     __syncthreads();
-    for (int g = 0; g < a.ngates; ++g) {
+    for (int g = 0; g < ngates; ++g) {
         // g is uniform; say so, so that descriptor reads become scalar loads
         const TileGate* __restrict__ G = gates + __builtin_amdgcn_readfirstlane(g);
         if (G->n_outer > 0 && !outer_holds(G, (uint64_t)obase)) continue;  // uniform over the workgroup
         const T* U = reinterpret_cast<const T*>(blob + G->u_off);
-        const uint16_t* bases = reinterpret_cast<const uint16_t*>(blob + G->bases_off);
+        const uint16_t* bases =
+            G->bases_off == kDecodeBases ? nullptr : reinterpret_cast<const uint16_t*>(blob + G->bases_off);
         if (G->kind == kDense) {
             switch (G->M) {
 #define QD_DENSE_CASE(m) \
@@ -183,7 +188,43 @@ __global__ __launch_bounds__(kFuseBlock) void fused_tile(typename Cx<R>::T* __re
         }
         __syncthreads();
     }
-    move_tile<T, I, false>(psi, tile, obase, a, run_off);
+    move_tile<T, I, false>(psi, tile, obase, geo, run_off);
+}
+
+template <typename R, typename I>
+__global__ __launch_bounds__(kFuseBlock) void fused_tile(typename Cx<R>::T* __restrict__ psi, const FusedArgs<I> a,
+                                                         const TileGate* __restrict__ gates,
+                                                         const unsigned char* __restrict__ blob,
+                                                         const I* __restrict__ run_off) {
+    using T = typename Cx<R>::T;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* tile = reinterpret_cast<T*>(smem_raw);
+    const I obase = decode_base<I>(a.outer, (I)xcd_block());
+    const TileGeom geo{a.tile, a.L, a.chunks_per_run, a.nchunks, a.cdiv};
+    process_tile<R, I>(psi, tile, obase, geo, a.ngates, gates, blob, run_off);
+}
+
+// A batched round: workgroup b processes tile (b - first_block) of the item
+// whose block range holds b (binary search over the items' first blocks).
+template <typename R>
+__global__ __launch_bounds__(kFuseBlock) void batch_tile(const BatchItem* __restrict__ items, int nitems,
+                                                         const unsigned char* __restrict__ blob) {
+    using T = typename Cx<R>::T;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* tile = reinterpret_cast<T*>(smem_raw);
+    const uint32_t b = xcd_block();
+    int lo = 0, hi = nitems - 1;
+    while (lo < hi) {  // last item with first_block <= b (uniform)
+        const int mid = (lo + hi + 1) >> 1;
+        if (items[mid].first_block <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const BatchItem* __restrict__ it = items + __builtin_amdgcn_readfirstlane(lo);
+    const uint32_t obase = decode_base<uint32_t>(it->outer, b - it->first_block);
+    const TileGeom geo{it->tile, it->L, it->chunks_per_run, it->nchunks, it->cdiv};
+    process_tile<R, uint32_t>(reinterpret_cast<T*>(it->psi), tile, obase, geo, it->ngates,
+                              reinterpret_cast<const TileGate*>(blob + it->gates_off), blob,
+                              reinterpret_cast<const uint32_t*>(blob + it->run_off_off));
 }
 
 template <typename R, typename I>
@@ -215,6 +256,29 @@ static hipError_t run_fused(const FusedLaunch& f, void* psi, const void* dblob, 
                        static_cast<T*>(psi), a, reinterpret_cast<const TileGate*>(b + f.gates_off), b,
                        reinterpret_cast<const I*>(b + f.run_off_off));
     return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t run_batch(const void* ditems, int nitems, uint32_t nblocks, uint32_t max_tile, const void* dblob,
+                            hipStream_t st) {
+    using T = typename Cx<R>::T;
+    const size_t shmem = (size_t)max_tile * sizeof(T);
+    if (shmem > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&batch_tile<R>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((batch_tile<R>), dim3(nblocks), dim3(kFuseBlock), shmem, st,
+                       static_cast<const BatchItem*>(ditems), nitems, static_cast<const unsigned char*>(dblob));
+    return hipGetLastError();
+}
+
+hipError_t launch_batch(int precision, const void* ditems, int nitems, uint32_t nblocks, uint32_t max_tile,
+                        const void* dblob, hipStream_t st) {
+    if (nitems <= 0 || nblocks == 0) return hipSuccess;
+    if (nblocks > 0x7fffffffu) return hipErrorInvalidValue;
+    return precision == kC128 ? run_batch<double>(ditems, nitems, nblocks, max_tile, dblob, st)
+                              : run_batch<float>(ditems, nitems, nblocks, max_tile, dblob, st);
 }
 
 hipError_t launch_fused(const FusedLaunch& f, int precision, void* psi, const void* dblob, hipStream_t st) {

@@ -34,7 +34,7 @@ void put_complex(unsigned char* dst, double re, double im) {
 }  // namespace
 
 int build_fused(const int32_t* dims, int n, int precision, const CircuitGate* gates, const std::vector<int>& idx,
-                const std::vector<int>& S, int p_low, PassPlan* out, std::string* err) {
+                const std::vector<int>& S, int p_low, bool tables, PassPlan* out, std::string* err) {
     uint64_t s[QD_MAX_QUDITS];
     s[0] = 1;
     for (int i = 1; i < n; ++i) s[i] = s[i - 1] * (uint64_t)dims[i - 1];
@@ -103,10 +103,16 @@ int build_fused(const int32_t* dims, int n, int precision, const CircuitGate* ga
             return rc;
         }
         if (gp->category == kIdentity) continue;
-        // Tile-local class bases, decoded once here for every tile.
+        if (gp->nseg > kTileMaxSeg) {
+            delete gp;
+            *err = "tile-local plan has too many segments";
+            return QD_ERR_NOT_SUPPORTED;
+        }
         t.n_classes = (uint32_t)gp->n_classes;
-        t.bases_off = (uint32_t)udata.size();
-        {
+        t.dec = make_decode<uint32_t, kTileMaxSeg>(*gp);
+        t.bases_off = kDecodeBases;
+        if (tables) {  // tile-local class bases, decoded once here for every tile
+            t.bases_off = (uint32_t)udata.size();
             const Decode<uint64_t> dec = make_decode<uint64_t>(*gp);
             udata.resize(align_up(udata.size() + 2 * (size_t)gp->n_classes, 16));
             uint16_t* b = reinterpret_cast<uint16_t*>(udata.data() + t.bases_off);
@@ -148,7 +154,7 @@ int build_fused(const int32_t* dims, int n, int precision, const CircuitGate* ga
     const size_t data_off = align_up(sizeof(TileGate) * tg.size(), 16);
     for (TileGate& t : tg) {
         t.u_off += (uint32_t)data_off;
-        t.bases_off += (uint32_t)data_off;
+        if (t.bases_off != kDecodeBases) t.bases_off += (uint32_t)data_off;
     }
     f.run_off_off = align_up(data_off + udata.size(), 16);
     const bool narrow = D < (1ull << 31);
@@ -213,7 +219,7 @@ int plan_circuit(const int32_t* dims, int n, int precision, const CircuitGate* g
     auto close_pass = [&]() -> int {
         if (cur.empty()) return QD_OK;
         PassPlan pp;
-        if (cur.size() == 1) {
+        if (cur.size() == 1 && !opt.single_as_fused) {
             pp.fused = false;
             pp.gates = cur;
         } else {
@@ -227,7 +233,7 @@ int plan_circuit(const int32_t* dims, int n, int precision, const CircuitGate* g
             std::vector<int> S;
             for (int q = 0; q < n; ++q)
                 if (inS[q]) S.push_back(q);
-            int r2 = build_fused(dims, n, precision, gates, cur, S, p_low, &pp, err);
+            int r2 = build_fused(dims, n, precision, gates, cur, S, p_low, opt.tables, &pp, err);
             if (r2) return r2;
         }
         out.push_back(std::move(pp));

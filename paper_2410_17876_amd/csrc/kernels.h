@@ -53,6 +53,11 @@ struct FusedLaunch {
 };
 hipError_t launch_fused(const FusedLaunch& f, int precision, void* psi, const void* dblob, hipStream_t stream);
 
+// A batched round (fused.h BatchItem): ditems/dblob are device copies; nblocks =
+// total tiles over all items; max_tile = largest tile (LDS per workgroup).
+hipError_t launch_batch(int precision, const void* ditems, int nitems, uint32_t nblocks, uint32_t max_tile,
+                        const void* dblob, hipStream_t stream);
+
 // Reductions and fills (reduce.hip).
 constexpr int kRedBlocks = 1024;
 hipError_t launch_sumsq(const void* psi, int precision, uint64_t D, double* scratch /* kRedBlocks+1 */,

@@ -189,3 +189,14 @@ def test_circuit_validation_rejects_bad_gate():
     with pytest.raises(qd.QDError) as e:
         qd.circuit_plan([2, 2], gates)
     assert "gate 1" in str(e.value)
+
+
+def test_batch_api_host_validation():
+    lib = qd.lib
+    h = C.c_void_p()
+    assert lib.qd_batch_create(3, C.byref(h)) == -1
+    assert lib.qd_batch_create(2, C.byref(h)) == 0
+    assert lib.qd_batch_apply(h, None, None, None, 0, None) == 0   # nothing to do
+    assert lib.qd_batch_apply(h, None, None, None, 2, None) == -1
+    assert lib.qd_batch_apply(None, None, None, None, 1, None) == -1
+    assert lib.qd_batch_destroy(h) == 0

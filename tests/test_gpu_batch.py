@@ -1,0 +1,107 @@
+"""Batched execution (qd_batch_apply): every state's result must be bitwise the
+same as running its gate list alone through qd_apply_circuit with the same
+tile options, and match the FP64 oracle within the tolerances."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import assert_close, rand_state
+from qd_inputs import Gate, circuits, haar, shift
+
+pytestmark = pytest.mark.gpu
+
+
+def qd():
+    import paper_2410_17876_amd as q
+    return q
+
+
+def small_specs(rng, count, cap):
+    out = []
+    while len(out) < count:
+        n = int(rng.integers(2, 9))
+        dims = [int(x) for x in rng.integers(2, 6, size=n)]
+        if math.prod(dims) <= cap:
+            out.append(dims)
+    return out
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_batch_equals_alone_and_oracle(precision):
+    rng = np.random.default_rng(21)
+    dims_list = small_specs(rng, 14, 20000) + [[2, 2, 2, 2, 2, 2], [3, 3, 3, 2, 2, 5, 2]]
+    lists = [circuits.random_circuit(d, int(rng.integers(20, 80)), 900 + i) for i, d in enumerate(dims_list)]
+    # a gate too large for a tile (M = 27) forces a separate launch inside a round
+    lists[-1] = lists[-1][:10] + [Gate((0, 1, 2), haar(27, rng))] + lists[-1][10:]
+    lists[3] = [Gate((0,), shift(dims_list[3][0]), (1,), (1,))] + lists[3]
+    psi0 = [rand_state(rng, math.prod(d)) for d in dims_list]
+    tile = 1024 if precision == "c128" else 2048
+    runner = qd().batch.BatchRunner(dims_list, precision)
+    for st, p in zip(runner.states, psi0):
+        st.set_amplitudes(p)
+    info = runner.run(lists, tile_amps=tile, min_run=32)
+    assert info["rounds"] >= 1 and info["items"] >= len(dims_list)
+    for i, (d, gl, p) in enumerate(zip(dims_list, lists, psi0)):
+        alone = qd().State(d, precision, init=None).set_amplitudes(p)
+        alone.run_circuit(gl, tile_amps=tile, min_run=32)
+        got = runner.states[i].amplitudes()
+        assert np.array_equal(got, alone.amplitudes()), f"state {i} differs from its solo run"
+        ref = p.copy() if precision == "c128" else (p.real.astype(np.float32).astype(np.float64) +
+                                                    1j * p.imag.astype(np.float32).astype(np.float64))
+        for g in gl:
+            oracle.apply_gate(d, ref, g)
+        assert_close(got, ref, precision, f"state {i} dims {d}")
+    runner.close()
+
+
+def test_batch_rounds_for_whole_register_tiles():
+    # registers that fit one tile run their whole circuit in a single round
+    rng = np.random.default_rng(22)
+    dims_list = [[2, 3, 2, 2], [5, 5, 3], [2] * 10]
+    lists = [circuits.random_circuit(d, 100, 40 + i) for i, d in enumerate(dims_list)]
+    runner = qd().batch.BatchRunner(dims_list, "c64")
+    info = runner.run(lists, tile_amps=2048, min_run=64)
+    assert info["rounds"] == 1 and info["items"] == 3
+    for st, d, gl in zip(runner.states, dims_list, lists):
+        assert_close(st.amplitudes(), oracle.run(d, gl), "c64", f"dims {d}")
+    runner.close()
+
+
+def test_batch_errors_leave_states_untouched():
+    q = qd()
+    rng = np.random.default_rng(23)
+    a = q.State([2, 3, 2], "c128", init=None).set_amplitudes(rand_state(rng, 12))
+    b = q.State([3, 3], "c128", init=None).set_amplitudes(rand_state(rng, 9))
+    c64 = q.State([2, 2], "c64")
+    before = [a.amplitudes(), b.amplitudes()]
+    batch = q.Batch("c128")
+    good = [Gate((0,), haar(2, rng))]
+    with pytest.raises(q.QDError):
+        batch.apply([a, c64], [good, good])  # precision mismatch
+    with pytest.raises(q.QDError):
+        batch.apply([a, a], [good, good])  # duplicate state
+    with pytest.raises(q.QDError):
+        batch.apply([a, b], [good, [Gate((0, 0), np.eye(9))]])  # invalid gate in the second list
+    assert np.array_equal(a.amplitudes(), before[0]) and np.array_equal(b.amplitudes(), before[1])
+    batch.close()
+
+
+@pytest.mark.parametrize("precision", ["c64", "c128"])
+def test_batched_workload_sample_equals_alone(precision):
+    # 48 circuits of the batched workload (6..16 qudits, d in 2..5, D <= 1e6), depth capped at 120
+    specs = circuits.batched_specs(count=48, depth_hi=120)
+    lists = [s.gates() for s in specs]
+    runner = qd().batch.BatchRunner([s.dims for s in specs], precision)
+    runner.run(lists)
+    rng = np.random.default_rng(24)
+    for i in rng.choice(len(specs), 6, replace=False):
+        alone = qd().State(specs[i].dims, precision)
+        alone.run_circuit(lists[i])
+        assert np.array_equal(runner.states[i].amplitudes(), alone.amplitudes()), f"circuit {i}"
+        alone.close()
+    for st in runner.states:
+        n = st.norm()
+        assert abs(n - 1.0) < (1e-12 if precision == "c128" else 1e-4)
+    runner.close()
