@@ -237,24 +237,33 @@ def run_batched(qd, precision, steps, warmup, tune_cache):
         updates += sum(i["updated"] for i in infos)
         npass = len(qd.circuit_plan(s.dims, gl, precision, tile_amps=tile, min_run=run_len))
         pass_bytes += npass * 2 * s.D * ab
-    for w in range(warmup):
-        info = runner.run(lists, tile_amps=tile, min_run=run_len)
-        log(f"batched {precision}: warmup {w}: {info['rounds']} rounds, {info['items']} items, {info['seconds']:.3f} s")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        info = runner.run(lists, tile_amps=tile, min_run=run_len)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    t0 = time.time()
+    plan = runner.compile(lists, tile_amps=tile, min_run=run_len)
+    log(f"batched {precision}: compiled {plan.rounds} rounds, {plan.items} items in {time.time() - t0:.1f} s")
+    timing = {}
+    for mode in ("eager", "graph"):
+        for w in range(warmup):
+            plan.run(graph=(mode == "graph"))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.run(graph=(mode == "graph"))
+        torch.cuda.synchronize()
+        timing[mode] = time.perf_counter() - t0
+        log(f"batched {precision}: {steps} timed steps ({mode} replay) in {timing[mode]:.3f} s")
+    wall = timing["graph"]
     norms = [st.norm() for st in runner.states[:8]]
+    rounds, items = plan.rounds, plan.items
+    plan.close()
     runner.close()
     torch.cuda.empty_cache()
-    log(f"batched {precision}: {steps} timed steps in {wall:.3f} s; norms of the first states {norms[:3]}")
+    log(f"batched {precision}: norms of the first states {norms[:3]}")
     achieved = pass_bytes * steps / wall / 1e9
     return {"value": updates * steps / wall, "unit": "updates/s", "dtype": "f64" if precision == "c128" else "f32",
-            "ms_per_step": 1e3 * wall / steps, "launch_rounds_per_step": info["rounds"],
-            "items_per_step": info["items"], "autotuned": {"tile_amps": tile, "min_run": run_len,
-                                                           "timings_s": tuned.get("timings_s")},
+            "ms_per_step": 1e3 * wall / steps, "ms_per_step_eager_launches": 1e3 * timing["eager"] / steps,
+            "launch_rounds_per_step": rounds, "items_per_step": items,
+            "path": "compiled batch replayed as one hipGraph per step",
+            "autotuned": {"tile_amps": tile, "min_run": run_len, "timings_s": tuned.get("timings_s")},
             "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                          "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": None, "kernel": "batch_tile",
                          "note": "whole-run average over all rounds: 2 x D x bytes per (state, pass)"}}

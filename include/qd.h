@@ -216,6 +216,24 @@ int qd_batch_destroy(qd_batch* b);
 int qd_batch_apply(qd_batch* b, qd_state* const* states, const qd_gate_desc* const* gates, const int32_t* counts,
                    int32_t nstates, qd_circuit_options* opts);
 
+/* A compiled batch: qd_batch_apply's rounds planned once, with all their
+ * descriptors uploaded to one device buffer, for gate lists that are run many
+ * times. The states (and their buffers) must outlive the plan, and the plan
+ * replays the same gates on their current contents. Every pass must fit a
+ * batch item (classes of at most 16 amplitudes), else QD_ERR_NOT_SUPPORTED.
+ * opts as for qd_batch_apply (out fields filled). Synchronous (uploads). */
+typedef struct qd_batch_plan qd_batch_plan;
+int qd_batch_compile(qd_state* const* states, const qd_gate_desc* const* gates, const int32_t* counts,
+                     int32_t nstates, qd_circuit_options* opts, qd_batch_plan** out);
+
+/* Enqueue all rounds of the plan on the states' stream: one launch per round,
+ * or, with use_graph != 0, one launch of a hipGraph captured from those
+ * launches on the first such call. Asynchronous. */
+int qd_batch_plan_run(qd_batch_plan* plan, int32_t use_graph);
+
+/* Wait for the plan's stream, then free the plan (not the states). */
+int qd_batch_plan_destroy(qd_batch_plan* plan);
+
 /* ||psi||_2 = sqrt(sum_j |a_j|^2), summed in FP64 on the device in a fixed
  * order (the same result for the same state, run after run). Synchronous. */
 int qd_norm(const qd_state* s, double* out);

@@ -11,7 +11,7 @@ from __future__ import annotations
 import time
 from typing import List, Optional, Sequence
 
-from .binding import Batch, GateList, State
+from .binding import Batch, BatchPlan, GateList, State
 
 
 class BatchRunner:
@@ -32,6 +32,10 @@ class BatchRunner:
         self.states[0].synchronize()
         info["seconds"] = time.perf_counter() - t0
         return info
+
+    def compile(self, gate_lists: Sequence, tile_amps: int = 0, min_run: int = 0) -> BatchPlan:
+        """Plan and upload the rounds once; replay them with plan.run(graph=...)."""
+        return BatchPlan(self.states, gate_lists, tile_amps=tile_amps, min_run=min_run)
 
     def updates(self, gate_lists) -> int:
         """Gate-amplitude updates of the gate lists (as counted per gate by the library)."""

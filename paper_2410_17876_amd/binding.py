@@ -79,6 +79,10 @@ def _load() -> C.CDLL:
         "qd_batch_destroy": [vp],
         "qd_batch_apply": [vp, C.POINTER(vp), C.POINTER(C.POINTER(GateDesc)), i32p, C.c_int32,
                            C.POINTER(CircuitOptions)],
+        "qd_batch_compile": [C.POINTER(vp), C.POINTER(C.POINTER(GateDesc)), i32p, C.c_int32,
+                             C.POINTER(CircuitOptions), C.POINTER(vp)],
+        "qd_batch_plan_run": [vp, C.c_int32],
+        "qd_batch_plan_destroy": [vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -310,6 +314,45 @@ class State:
             pass
 
 
+def _batch_args(states, gate_lists):
+    n = len(states)
+    if len(gate_lists) != n:
+        raise ValueError("one gate list per state")
+    gls = [g if isinstance(g, GateList) else GateList(g) for g in gate_lists]
+    hs = (C.c_void_p * max(1, n))(*[st.handle for st in states])
+    gp = (C.POINTER(GateDesc) * max(1, n))(*[C.cast(g.descs, C.POINTER(GateDesc)) for g in gls])
+    counts = np.array([len(g) for g in gls] or [0], dtype=np.int32)
+    return gls, hs, gp, counts
+
+
+class BatchPlan:
+    """A compiled batch (qd_batch_compile): replay the same gate lists on the states."""
+
+    def __init__(self, states, gate_lists, tile_amps=0, min_run=0):
+        self.states = list(states)
+        self._keep = _batch_args(self.states, gate_lists)
+        gls, hs, gp, counts = self._keep
+        opts = _options(True, tile_amps, min_run)
+        self._h = C.c_void_p()
+        check(lib.qd_batch_compile(hs, gp, counts.ctypes.data_as(C.POINTER(C.c_int32)), len(self.states),
+                                   C.byref(opts), C.byref(self._h)))
+        self.rounds, self.items = opts.passes, opts.fused_passes
+
+    def run(self, graph: bool = False) -> None:
+        check(lib.qd_batch_plan_run(self._h, 1 if graph else 0))
+
+    def close(self) -> None:
+        if self._h:
+            lib.qd_batch_plan_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Batch:
     """A batch context (qd_batch): advances many independent states together."""
 
@@ -321,12 +364,7 @@ class Batch:
     def apply(self, states, gate_lists, tile_amps=0, min_run=0) -> dict:
         """Apply gate_lists[i] to states[i] for all i (qd_batch_apply)."""
         n = len(states)
-        if len(gate_lists) != n:
-            raise ValueError("one gate list per state")
-        gls = [g if isinstance(g, GateList) else GateList(g) for g in gate_lists]
-        hs = (C.c_void_p * max(1, n))(*[st.handle for st in states])
-        gp = (C.POINTER(GateDesc) * max(1, n))(*[C.cast(g.descs, C.POINTER(GateDesc)) for g in gls])
-        counts = np.array([len(g) for g in gls] or [0], dtype=np.int32)
+        gls, hs, gp, counts = _batch_args(states, gate_lists)
         opts = _options(True, tile_amps, min_run)
         check(lib.qd_batch_apply(self._h, hs, gp, counts.ctypes.data_as(C.POINTER(C.c_int32)), n, C.byref(opts)))
         return {"rounds": opts.passes, "items": opts.fused_passes}

@@ -564,18 +564,39 @@ int qd_batch_destroy(qd_batch* b) {
     return QD_OK;
 }
 
-int qd_batch_apply(qd_batch* b, qd_state* const* states, const qd_gate_desc* const* gates, const int32_t* counts,
-                   int32_t nstates, qd_circuit_options* opts) {
-    if (!b) return set_err(QD_ERR_INVALID_ARGUMENT, "batch is null");
+}  // extern "C"
+
+namespace {
+
+// One launch round of a batch on the host: the round's blob (the pass blobs of
+// its items, then the BatchItem array at items_off) and the states whose pass in
+// this round runs as its own launch (a gate too large for a tile, or an outer
+// decode that does not fit a batch item).
+struct HostRound {
+    std::vector<unsigned char> blob;
+    size_t items_off = 0;
+    int nitems = 0;
+    uint64_t nblocks = 0;
+    uint32_t max_tile = 0;
+    std::vector<int> singles;
+};
+
+struct BatchInput {
+    std::vector<std::vector<CircuitGate>> cg;
+    std::vector<std::vector<PassPlan>> plans;
+    size_t rounds = 0;
+};
+
+int batch_validate_and_plan(int precision, qd_state* const* states, const qd_gate_desc* const* gates,
+                            const int32_t* counts, int32_t nstates, const qd_circuit_options* opts, BatchInput& in) {
     if (nstates < 0) return set_err(QD_ERR_INVALID_ARGUMENT, "negative state count");
-    if (nstates == 0) return QD_OK;
-    if (!states || !gates || !counts) return set_err(QD_ERR_INVALID_ARGUMENT, "states, gates or counts is null");
-    // Validate everything before enqueuing anything.
-    std::vector<std::vector<CircuitGate>> cg(nstates);
+    if (nstates > 0 && (!states || !gates || !counts))
+        return set_err(QD_ERR_INVALID_ARGUMENT, "states, gates or counts is null");
+    in.cg.assign(nstates, {});
     for (int i = 0; i < nstates; ++i) {
         const qd_state* s = states[i];
         if (!s) return set_err(QD_ERR_INVALID_ARGUMENT, "state " + std::to_string(i) + " is null");
-        if (s->precision != b->precision)
+        if (s->precision != precision)
             return set_err(QD_ERR_INVALID_ARGUMENT, "state " + std::to_string(i) + " has another precision");
         if (s->device != states[0]->device || s->stream != states[0]->stream)
             return set_err(QD_ERR_INVALID_ARGUMENT, "all states of a batch must share one device and stream");
@@ -583,113 +604,275 @@ int qd_batch_apply(qd_batch* b, qd_state* const* states, const qd_gate_desc* con
             return set_err(QD_ERR_NOT_SUPPORTED, "batched states must have fewer than 2^31 amplitudes");
         for (int j = 0; j < i; ++j)
             if (states[j] == s) return set_err(QD_ERR_INVALID_ARGUMENT, "a state appears twice in a batch");
-        int rc = circuit_gates(s->dims, s->n, gates[i], counts[i], cg[i]);
+        int rc = circuit_gates(s->dims, s->n, gates[i], counts[i], in.cg[i]);
         if (rc) return set_err(rc, "state " + std::to_string(i) + ": " + qd_last_error());
     }
     CircuitOptions co;
-    int rc = circuit_options(opts, b->precision, &co);
+    int rc = circuit_options(opts, precision, &co);
     if (rc) return rc;
     co.fuse = true;
     co.tables = false;
     co.single_as_fused = true;
-    std::vector<std::vector<PassPlan>> plans(nstates);
-    size_t rounds = 0;
+    in.plans.assign(nstates, {});
+    in.rounds = 0;
     for (int i = 0; i < nstates; ++i) {
         std::string err;
-        rc = plan_circuit(states[i]->dims, states[i]->n, b->precision, cg[i].data(), counts[i], co, plans[i], &err);
+        rc = plan_circuit(states[i]->dims, states[i]->n, precision, in.cg[i].data(), counts[i], co, in.plans[i], &err);
         if (rc) return set_err(rc, "state " + std::to_string(i) + ": " + err);
-        rounds = std::max(rounds, plans[i].size());
+        in.rounds = std::max(in.rounds, in.plans[i].size());
     }
+    return QD_OK;
+}
+
+int build_round(qd_state* const* states, int32_t nstates, const BatchInput& in, size_t r, HostRound& out) {
+    out = HostRound();
+    std::vector<BatchItem> items;
+    for (int i = 0; i < nstates; ++i) {
+        if (r >= in.plans[i].size()) continue;
+        const PassPlan& pp = in.plans[i][r];
+        if (!pp.fused || pp.launch.outer_nseg > kTileMaxSeg) {
+            out.singles.push_back(i);
+            continue;
+        }
+        if (pp.launch.ngates == 0) continue;
+        const FusedLaunch& f = pp.launch;
+        const size_t base = (out.blob.size() + 15) / 16 * 16;
+        out.blob.resize(base + pp.blob.size());
+        std::memcpy(out.blob.data() + base, pp.blob.data(), pp.blob.size());
+        TileGate* tg = reinterpret_cast<TileGate*>(out.blob.data() + base + f.gates_off);
+        for (int g = 0; g < f.ngates; ++g) {
+            tg[g].u_off += (uint32_t)base;
+            if (tg[g].bases_off != kDecodeBases) tg[g].bases_off += (uint32_t)base;
+        }
+        BatchItem it;
+        std::memset(&it, 0, sizeof it);
+        it.psi = reinterpret_cast<uint64_t>(states[i]->psi);
+        it.outer.n_classes = (uint32_t)f.n_tiles;
+        it.outer.ctrl_off = 0;
+        it.outer.nseg = f.outer_nseg;
+        for (int g = 0; g < kTileMaxSeg; ++g) {
+            it.outer.size[g] = g < f.outer_nseg ? (uint32_t)f.outer_size[g] : 1u;
+            it.outer.stride[g] = g < f.outer_nseg ? (uint32_t)f.outer_stride[g] : 0u;
+            it.outer.div[g] = make_fast_div<uint32_t>(g < f.outer_nseg ? f.outer_size[g] : 1);
+        }
+        it.tile = f.tile;
+        it.L = f.L;
+        it.chunks_per_run = (f.L + 63) / 64;
+        it.nchunks = (f.tile / f.L) * it.chunks_per_run;
+        it.cdiv = make_fast_div<uint32_t>(it.chunks_per_run);
+        it.ngates = f.ngates;
+        it.gates_off = (uint32_t)(base + f.gates_off);
+        it.run_off_off = (uint32_t)(base + f.run_off_off);
+        it.first_block = (uint32_t)out.nblocks;
+        out.nblocks += f.n_tiles;
+        out.max_tile = std::max(out.max_tile, f.tile);
+        items.push_back(it);
+    }
+    if (out.nblocks >= 0x7fffffffull) return set_err(QD_ERR_NOT_SUPPORTED, "batched round too large");
+    if (out.blob.size() > 0xffffffffull) return set_err(QD_ERR_NOT_SUPPORTED, "batched round blob too large");
+    out.nitems = (int)items.size();
+    if (!items.empty()) {
+        out.items_off = (out.blob.size() + 15) / 16 * 16;
+        out.blob.resize(out.items_off + items.size() * sizeof(BatchItem));
+        std::memcpy(out.blob.data() + out.items_off, items.data(), items.size() * sizeof(BatchItem));
+    }
+    return QD_OK;
+}
+
+// The launch of one state's own pass inside a round (see HostRound::singles).
+int enqueue_round_single(qd_state* s, const BatchInput& in, int i, size_t r, hipStream_t st) {
+    const PassPlan& pp = in.plans[i][r];
+    if (pp.fused) {
+        const void* dblob = nullptr;
+        int rc = stage(s, pp.blob.data(), pp.blob.size(), &dblob);
+        if (rc) return rc;
+        QD_HIP(launch_fused(pp.launch, s->precision, s->psi, dblob, st), "fused launch");
+        return QD_OK;
+    }
+    const CircuitGate& g = in.cg[i][pp.gates[0]];
+    GatePlan p;
+    std::string err;
+    int rc = plan_gate(s->dims, s->n, g.targets, g.k, g.controls, g.values, g.m, g.U, &p, &err);
+    if (rc) return set_err(rc, err);
+    return enqueue_single(s, p, g.U);
+}
+
+}  // namespace
+
+// A compiled batch: all rounds' blobs in one device buffer, launched by
+// qd_batch_plan_run without any host planning or uploads (and, when asked,
+// replayed as one captured hipGraph).
+struct qd_batch_plan {
+    int precision = 0;
+    std::vector<qd_state*> states;
+    hipStream_t stream = nullptr;
+    struct Round {
+        size_t blob_off = 0;
+        size_t items_off = 0;
+        int nitems = 0;
+        uint32_t nblocks = 0;
+        uint32_t max_tile = 0;
+    };
+    std::vector<Round> rounds;
+    int32_t items_total = 0;
+    unsigned char* dev = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+int qd_batch_apply(qd_batch* b, qd_state* const* states, const qd_gate_desc* const* gates, const int32_t* counts,
+                   int32_t nstates, qd_circuit_options* opts) {
+    if (!b) return set_err(QD_ERR_INVALID_ARGUMENT, "batch is null");
+    if (nstates == 0) return QD_OK;
+    BatchInput in;
+    int rc = batch_validate_and_plan(b->precision, states, gates, counts, nstates, opts, in);
+    if (rc) return rc;
     qd_state* s0 = states[0];
     rc = use_device(s0);
     if (rc) return rc;
     hipStream_t st = s0->stream;
     int32_t items_total = 0;
-    GatePlan p;
-    for (size_t r = 0; r < rounds; ++r) {
+    HostRound hr;
+    for (size_t r = 0; r < in.rounds; ++r) {
         // Round r: pass r of every state that has one; fused passes go into one
-        // launch, any one-gate sweep (a gate too large for a tile) runs after it.
-        std::vector<BatchItem> items;
-        std::vector<unsigned char> blob;
-        std::vector<int> singles;
-        uint64_t nblocks = 0;
-        uint32_t max_tile = 0;
-        for (int i = 0; i < nstates; ++i) {
-            if (r >= plans[i].size()) continue;
-            const PassPlan& pp = plans[i][r];
-            if (!pp.fused || pp.launch.outer_nseg > kTileMaxSeg) {
-                singles.push_back(i);
-                continue;
-            }
-            if (pp.launch.ngates == 0) continue;
-            const FusedLaunch& f = pp.launch;
-            const size_t base = (blob.size() + 15) / 16 * 16;
-            blob.resize(base + pp.blob.size());
-            std::memcpy(blob.data() + base, pp.blob.data(), pp.blob.size());
-            TileGate* tg = reinterpret_cast<TileGate*>(blob.data() + base + f.gates_off);
-            for (int g = 0; g < f.ngates; ++g) {
-                tg[g].u_off += (uint32_t)base;
-                if (tg[g].bases_off != kDecodeBases) tg[g].bases_off += (uint32_t)base;
-            }
-            BatchItem it;
-            std::memset(&it, 0, sizeof it);
-            it.psi = reinterpret_cast<uint64_t>(states[i]->psi);
-            it.outer.n_classes = (uint32_t)f.n_tiles;
-            it.outer.ctrl_off = 0;
-            it.outer.nseg = f.outer_nseg;
-            for (int g = 0; g < kTileMaxSeg; ++g) {
-                it.outer.size[g] = g < f.outer_nseg ? (uint32_t)f.outer_size[g] : 1u;
-                it.outer.stride[g] = g < f.outer_nseg ? (uint32_t)f.outer_stride[g] : 0u;
-                it.outer.div[g] = make_fast_div<uint32_t>(g < f.outer_nseg ? f.outer_size[g] : 1);
-            }
-            it.tile = f.tile;
-            it.L = f.L;
-            it.chunks_per_run = (f.L + 63) / 64;
-            it.nchunks = (f.tile / f.L) * it.chunks_per_run;
-            it.cdiv = make_fast_div<uint32_t>(it.chunks_per_run);
-            it.ngates = f.ngates;
-            it.gates_off = (uint32_t)(base + f.gates_off);
-            it.run_off_off = (uint32_t)(base + f.run_off_off);
-            it.first_block = (uint32_t)nblocks;
-            nblocks += f.n_tiles;
-            max_tile = std::max(max_tile, f.tile);
-            items.push_back(it);
-        }
-        if (nblocks >= 0x7fffffffull) return set_err(QD_ERR_NOT_SUPPORTED, "batched round too large");
-        if (!items.empty()) {
-            const size_t items_off = (blob.size() + 15) / 16 * 16;
-            blob.resize(items_off + items.size() * sizeof(BatchItem));
-            std::memcpy(blob.data() + items_off, items.data(), items.size() * sizeof(BatchItem));
+        // launch, any pass that cannot join it runs right after it.
+        rc = build_round(states, nstates, in, r, hr);
+        if (rc) return rc;
+        if (hr.nitems) {
             const unsigned char* dblob = nullptr;
-            rc = batch_stage(b, blob, st, &dblob);
+            rc = batch_stage(b, hr.blob, st, &dblob);
             if (rc) return rc;
-            QD_HIP(launch_batch(b->precision, dblob + items_off, (int)items.size(), (uint32_t)nblocks, max_tile, dblob,
-                                st),
+            QD_HIP(launch_batch(b->precision, dblob + hr.items_off, hr.nitems, (uint32_t)hr.nblocks, hr.max_tile,
+                                dblob, st),
                    "batch launch");
-            items_total += (int32_t)items.size();
+            items_total += hr.nitems;
         }
-        for (int i : singles) {
-            const PassPlan& pp = plans[i][r];
-            qd_state* s = states[i];
-            if (pp.fused) {  // a fused pass whose outer decode does not fit a batch item
-                const void* dblob = nullptr;
-                rc = stage(s, pp.blob.data(), pp.blob.size(), &dblob);
-                if (rc) return rc;
-                QD_HIP(launch_fused(pp.launch, s->precision, s->psi, dblob, s->stream), "fused launch");
-                continue;
-            }
-            const CircuitGate& g = cg[i][pp.gates[0]];
-            std::string err;
-            rc = plan_gate(s->dims, s->n, g.targets, g.k, g.controls, g.values, g.m, g.U, &p, &err);
-            if (rc) return set_err(rc, err);
-            rc = enqueue_single(s, p, g.U);
+        for (int i : hr.singles) {
+            rc = enqueue_round_single(states[i], in, i, r, st);
             if (rc) return rc;
         }
     }
     if (opts) {
-        opts->passes = (int32_t)rounds;
+        opts->passes = (int32_t)in.rounds;
         opts->fused_passes = items_total;
     }
+    return QD_OK;
+}
+
+int qd_batch_compile(qd_state* const* states, const qd_gate_desc* const* gates, const int32_t* counts,
+                     int32_t nstates, qd_circuit_options* opts, qd_batch_plan** out) {
+    if (!out) return set_err(QD_ERR_INVALID_ARGUMENT, "out is null");
+    *out = nullptr;
+    if (nstates < 1 || !states || !states[0]) return set_err(QD_ERR_INVALID_ARGUMENT, "a plan needs at least one state");
+    const int precision = states[0]->precision;
+    BatchInput in;
+    int rc = batch_validate_and_plan(precision, states, gates, counts, nstates, opts, in);
+    if (rc) return rc;
+    qd_batch_plan* P = new qd_batch_plan();
+    P->precision = precision;
+    P->states.assign(states, states + nstates);
+    P->stream = states[0]->stream;
+    std::vector<unsigned char> all;
+    HostRound hr;
+    for (size_t r = 0; r < in.rounds; ++r) {
+        rc = build_round(states, nstates, in, r, hr);
+        if (rc == QD_OK && !hr.singles.empty())
+            rc = set_err(QD_ERR_NOT_SUPPORTED, "a compiled batch needs every pass to fit a batch item (tile gates "
+                                               "with at most 16 amplitudes per class); use qd_batch_apply");
+        if (rc) {
+            delete P;
+            return rc;
+        }
+        qd_batch_plan::Round R;
+        R.blob_off = (all.size() + 255) / 256 * 256;
+        R.items_off = hr.items_off;
+        R.nitems = hr.nitems;
+        R.nblocks = (uint32_t)hr.nblocks;
+        R.max_tile = hr.max_tile;
+        all.resize(R.blob_off + hr.blob.size());
+        std::memcpy(all.data() + R.blob_off, hr.blob.data(), hr.blob.size());
+        P->rounds.push_back(R);
+        P->items_total += hr.nitems;
+    }
+    rc = use_device(states[0]);
+    if (rc == QD_OK && !all.empty()) {
+        if (hipMalloc(reinterpret_cast<void**>(&P->dev), all.size()) != hipSuccess) {
+            P->dev = nullptr;
+            rc = set_err(QD_ERR_OUT_OF_MEMORY, "device allocation of the compiled batch failed");
+        } else {
+            hipError_t e = hipMemcpy(P->dev, all.data(), all.size(), hipMemcpyHostToDevice);
+            if (e != hipSuccess) rc = hip_err(e, "compiled batch upload");
+        }
+    }
+    if (rc) {
+        if (P->dev) (void)hipFree(P->dev);
+        delete P;
+        return rc;
+    }
+    if (opts) {
+        opts->passes = (int32_t)P->rounds.size();
+        opts->fused_passes = P->items_total;
+    }
+    *out = P;
+    return QD_OK;
+}
+
+namespace {
+hipError_t plan_enqueue(qd_batch_plan* P, hipStream_t st) {
+    for (const auto& R : P->rounds) {
+        if (!R.nitems) continue;
+        hipError_t e = launch_batch(P->precision, P->dev + R.blob_off + R.items_off, R.nitems, R.nblocks, R.max_tile,
+                                    P->dev + R.blob_off, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+}  // namespace
+
+int qd_batch_plan_run(qd_batch_plan* P, int32_t use_graph) {
+    if (!P) return set_err(QD_ERR_INVALID_ARGUMENT, "plan is null");
+    int rc = use_device(P->states[0]);
+    if (rc) return rc;
+    hipStream_t st = P->stream;
+    if (!use_graph) {
+        QD_HIP(plan_enqueue(P, st), "batch launch");
+        return QD_OK;
+    }
+    if (!P->exec) {
+        // Capture on a private stream so the caller's stream is never in capture mode.
+        hipStream_t cap = nullptr;
+        QD_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "capture stream");
+        hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t e2 = plan_enqueue(P, cap);
+            e = hipStreamEndCapture(cap, &P->graph);
+            if (e2 != hipSuccess) e = e2;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0);
+        (void)hipStreamDestroy(cap);
+        if (e != hipSuccess) {
+            if (P->graph) (void)hipGraphDestroy(P->graph);
+            P->graph = nullptr;
+            P->exec = nullptr;
+            return hip_err(e, "batch graph capture");
+        }
+    }
+    QD_HIP(hipGraphLaunch(P->exec, st), "batch graph launch");
+    return QD_OK;
+}
+
+int qd_batch_plan_destroy(qd_batch_plan* P) {
+    if (!P) return QD_OK;
+    if (!P->states.empty()) {
+        use_device(P->states[0]);
+        (void)hipStreamSynchronize(P->stream);
+    }
+    if (P->exec) (void)hipGraphExecDestroy(P->exec);
+    if (P->graph) (void)hipGraphDestroy(P->graph);
+    if (P->dev) (void)hipFree(P->dev);
+    delete P;
     return QD_OK;
 }
 

@@ -105,3 +105,35 @@ def test_batched_workload_sample_equals_alone(precision):
         n = st.norm()
         assert abs(n - 1.0) < (1e-12 if precision == "c128" else 1e-4)
     runner.close()
+
+
+@pytest.mark.parametrize("precision", ["c64", "c128"])
+def test_compiled_plan_and_graph_replays(precision):
+    # A compiled batch replays bitwise like qd_batch_apply, eagerly and as a
+    # captured graph; every graph replay is checked, with eager work between.
+    rng = np.random.default_rng(25)
+    dims_list = small_specs(rng, 10, 30000) + [[2] * 12]
+    lists = [circuits.random_circuit(d, int(rng.integers(20, 60)), 700 + i) for i, d in enumerate(dims_list)]
+    psi0 = [rand_state(rng, math.prod(d)) for d in dims_list]
+    q = qd()
+    ref = q.batch.BatchRunner(dims_list, precision)
+    for st, p in zip(ref.states, psi0):
+        st.set_amplitudes(p)
+    run = q.batch.BatchRunner(dims_list, precision)
+    for st, p in zip(run.states, psi0):
+        st.set_amplitudes(p)
+    plan = run.compile(lists, tile_amps=2048, min_run=64)
+    assert plan.rounds >= 1
+    for rep in range(4):
+        ref.run(lists, tile_amps=2048, min_run=64)
+        plan.run(graph=(rep > 0))
+        run.states[0].synchronize()
+        for i in range(len(dims_list)):
+            assert np.array_equal(run.states[i].amplitudes(), ref.states[i].amplitudes()), (rep, i)
+        # eager work on the same stream between graph replays
+        run.states[1].apply([0], haar(dims_list[1][0], rng))
+        ref.states[1].apply_gate(Gate((0,), np.eye(dims_list[1][0])))
+        ref.states[1].set_amplitudes(run.states[1].amplitudes())
+    plan.close()
+    ref.close()
+    run.close()
