@@ -269,6 +269,50 @@ def run_batched(qd, precision, steps, warmup, tune_cache):
                          "note": "whole-run average over all rounds: 2 x D x bytes per (state, pass)"}}
 
 
+def run_served(qd, n_closed, n_open, load):
+    """The served workload: requests with log-uniform sizes in [1e3, 1e8]
+    amplitudes (d in 2..7), depth 50..500 of the basic mix, complex64, admitted
+    under a 200 GB HBM budget. First the closed-loop capacity (all requests
+    present at t = 0), then open-loop Poisson arrivals at `load` x capacity."""
+    import torch
+    from qd_inputs import circuits
+
+    def build(count, qps):
+        t0 = time.time()
+        specs = circuits.served_requests(qps=qps, count=count)
+        reqs = qd.serve.requests_from_specs(specs)
+        log(f"served: {count} requests generated in {time.time() - t0:.1f} s "
+            f"(sum D = {sum(r.D for r in reqs):.3g}, gates = {sum(len(r.gates) for r in reqs)})")
+        return reqs
+
+    upd = lambda reqs: sum(qd.gate_info(r.dims, g.targets, g.U, g.controls, g.values, "c64")["updated"]
+                           for r in reqs for g in r.gates.gates)
+    warm = build(16, 1.0)
+    srv = qd.serve.Server("c64", budget_bytes=200e9, quantum=32)
+    srv.run(warm, realtime=False)
+    srv.close()
+    closed = build(n_closed, 1.0)
+    srv = qd.serve.Server("c64", budget_bytes=200e9, quantum=32)
+    rc = srv.run(closed, realtime=False)
+    srv.close()
+    cap = rc["throughput_rps"]
+    log(f"served: closed-loop capacity {cap:.1f} requests/s ({rc['wall_s']:.2f} s for {n_closed})")
+    opened = build(n_open, load * cap)
+    srv = qd.serve.Server("c64", budget_bytes=200e9, quantum=32)
+    ro = srv.run(opened, realtime=True)
+    srv.close()
+    torch.cuda.empty_cache()
+    log(f"served: open loop at {load:.2f} x capacity: p50 {ro['p50_ms']:.1f} ms, p99 {ro['p99_ms']:.1f} ms")
+    return {"workload": "Poisson arrivals, sizes log-uniform 1e3..1e8 amplitudes (d in 2..7), depth 50..500, "
+                        "basic gate mix, complex64, 200 GB HBM budget (seed 1003)",
+            "value": upd(opened) / ro["wall_s"], "unit": "updates/s", "dtype": "f32",
+            "closed_loop": {"requests": n_closed, "capacity_rps": cap, "wall_s": rc["wall_s"],
+                            "updates_per_s": upd(closed) / rc["wall_s"], "p50_ms": rc["p50_ms"],
+                            "p99_ms": rc["p99_ms"]},
+            "open_loop": dict(ro, offered_rps=load * cap, load=load),
+            "latency": "arrival -> final state resident and its FP64 norm returned to the host"}
+
+
 def cpu_baseline(qd, dims, gates, psi, seconds):
     import oracle
 
@@ -297,6 +341,10 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ququint", action="store_true", help="skip the 12-ququint MFMA workload")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-circuit batched workload")
+    ap.add_argument("--no-served", action="store_true", help="skip the served (continuous batching) workload")
+    ap.add_argument("--served-closed", type=int, default=120, help="requests in the closed-loop capacity run")
+    ap.add_argument("--served-open", type=int, default=240, help="requests in the open-loop run")
+    ap.add_argument("--served-load", type=float, default=0.8, help="open-loop load as a fraction of capacity")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "tune_cache.json"),
                     help="autotuner cache file")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -354,6 +402,8 @@ def main() -> int:
     if not args.no_batched:
         for p in (["c64", "c128"] if not args.no_c64 else ["c128"]):
             res[f"batched_{p}"] = run_batched(qd, p, args.steps, args.warmup, args.tune_cache)
+    if not args.no_served:
+        res["served"] = run_served(qd, args.served_closed, args.served_open, args.served_load)
     cpu = None
     if host is not None:
         cpu = cpu_baseline(qd, dims, gates, host, args.cpu_seconds)
@@ -393,6 +443,8 @@ def main() -> int:
             "value": r["value"], "unit": "updates/s", "dtype": "f32", "ms_per_step": r["ms_per_step"],
             "launches_per_step": r["launches_per_step"], "roofline": r["roofline"],
             "norm_last_step": r["norm_last_step"], "kernels": r["kernels"]}
+    if "served" in res:
+        line["runs"]["served_c64"] = res["served"]
     for p in ("c64", "c128"):
         if f"batched_{p}" in res:
             line["runs"][f"batched_{p}"] = dict(

@@ -122,7 +122,11 @@ int qd_state_create(const int32_t* dims, int32_t n, int32_t precision, qd_state*
 int qd_state_create_external(const int32_t* dims, int32_t n, int32_t precision, void* device_ptr,
                              uint64_t bytes, qd_state** out);
 
-/* Free the state (and its buffer if owned). Waits for its pending work. */
+/* Free the state (and its buffer if owned). If the state owns device memory
+ * (its buffer, or staging for large gates) this first waits for the state's
+ * stream; a state wrapping an external buffer is released without waiting,
+ * and the buffer's owner must not reuse it before the state's queued work has
+ * finished (stream-ordered allocators such as torch's do this by themselves). */
 int qd_state_destroy(qd_state* s);
 
 /* Run this state's work on hip_stream (a hipStream_t; null = default stream).
@@ -235,7 +239,9 @@ int qd_batch_plan_run(qd_batch_plan* plan, int32_t use_graph);
 int qd_batch_plan_destroy(qd_batch_plan* plan);
 
 /* ||psi||_2 = sqrt(sum_j |a_j|^2), summed in FP64 on the device in a fixed
- * order (the same result for the same state, run after run). Synchronous. */
+ * order (the same result for the same state, run after run). Synchronous: it
+ * waits for the state's stream. The device's reduction scratch is shared by all
+ * states and serialised by a lock. */
 int qd_norm(const qd_state* s, double* out);
 
 /* p_j = |a_j|^2 in FP64 for all j (Sec. 2: the squared amplitude of |j>).

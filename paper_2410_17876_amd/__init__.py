@@ -9,4 +9,4 @@ from .binding import (QD_C128, QD_C64, Batch, BatchPlan, GateInfo, GateList, QDE
 
 __all__ = ["Batch", "BatchPlan", "State", "QDError", "GateInfo", "GateList", "circuit_plan", "dim", "check_gate", "gate_info", "class_bases", "lib", "LIB_PATH",
            "QD_C64", "QD_C128"]
-from . import batch, tune  # noqa: E402  (batched runner, tile autotuner)
+from . import batch, serve, tune  # noqa: E402  (batched runner, server, tile autotuner)

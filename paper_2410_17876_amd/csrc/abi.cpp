@@ -4,9 +4,11 @@
 // work on amplitudes runs in the kernels of sweep.hip and reduce.hip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -91,8 +93,19 @@ struct qd_state {
     hipStream_t stream = nullptr;
     int device = 0;
     GateRing ring;
-    double* red = nullptr;  // kRedBlocks + 1 doubles of reduction scratch
 };
+
+namespace {
+
+// Reduction scratch: one buffer per device, shared by every state on it and
+// kept until the process ends (freeing device memory synchronises the device,
+// which a server retiring many states cannot afford). qd_norm holds the mutex
+// for its whole (synchronous) call, so concurrent callers never share it.
+constexpr int kMaxDevices = 64;
+std::mutex g_red_mu;
+double* g_red[kMaxDevices] = {};
+
+}  // namespace
 
 namespace {
 
@@ -244,10 +257,13 @@ int qd_state_create_external(const int32_t* dims, int32_t n, int32_t precision, 
 
 int qd_state_destroy(qd_state* s) {
     if (!s) return QD_OK;
-    use_device(s);
-    (void)hipStreamSynchronize(s->stream);
+    // Only device memory the state owns needs its pending work to finish first;
+    // an external buffer belongs to the caller, whose allocator orders reuse.
+    if (s->owned || s->ring.dev) {
+        use_device(s);
+        (void)hipStreamSynchronize(s->stream);
+    }
     s->ring.release();
-    if (s->red) (void)hipFree(s->red);
     if (s->owned && s->psi) (void)hipFree(s->psi);
     delete s;
     return QD_OK;
@@ -880,16 +896,18 @@ int qd_norm(const qd_state* s, double* out) {
     if (!s || !out) return set_err(QD_ERR_INVALID_ARGUMENT, "state or out is null");
     int rc = use_device(s);
     if (rc) return rc;
-    qd_state* ms = const_cast<qd_state*>(s);
-    if (!ms->red) {
-        if (hipMalloc(reinterpret_cast<void**>(&ms->red), (kRedBlocks + 1) * sizeof(double)) != hipSuccess) {
-            ms->red = nullptr;
+    if (s->device < 0 || s->device >= kMaxDevices) return set_err(QD_ERR_NOT_SUPPORTED, "device index too large");
+    std::lock_guard<std::mutex> lock(g_red_mu);
+    double*& red = g_red[s->device];
+    if (!red) {
+        if (hipMalloc(reinterpret_cast<void**>(&red), (kRedBlocks + 1) * sizeof(double)) != hipSuccess) {
+            red = nullptr;
             return set_err(QD_ERR_OUT_OF_MEMORY, "reduction scratch allocation failed");
         }
     }
-    QD_HIP(launch_sumsq(s->psi, s->precision, s->D, ms->red, s->stream), "norm");
+    QD_HIP(launch_sumsq(s->psi, s->precision, s->D, red, s->stream), "norm");
     double sum = 0.0;
-    QD_HIP(hipMemcpyAsync(&sum, ms->red + kRedBlocks, sizeof(double), hipMemcpyDeviceToHost, s->stream), "norm");
+    QD_HIP(hipMemcpyAsync(&sum, red + kRedBlocks, sizeof(double), hipMemcpyDeviceToHost, s->stream), "norm");
     QD_HIP(hipStreamSynchronize(s->stream), "norm");
     *out = std::sqrt(sum);
     return QD_OK;

@@ -1,0 +1,72 @@
+"""Continuous-batching server: results are the same alone and in the mix, the
+HBM budget is respected, and requests that arrive while others are on the GPU
+join them before those finish."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import assert_close
+from qd_inputs import circuits
+
+pytestmark = pytest.mark.gpu
+
+
+def qd():
+    import paper_2410_17876_amd as q
+    return q
+
+
+def make_requests(count, qps, lo, hi, depth_lo, depth_hi, seed):
+    reqs = circuits.served_requests(qps=qps, count=count, seed=seed, lo=lo, hi=hi, depth_lo=depth_lo,
+                                    depth_hi=depth_hi)
+    return reqs, qd().serve.requests_from_specs(reqs)
+
+
+@pytest.mark.parametrize("precision", ["c64", "c128"])
+def test_served_results_equal_alone_and_oracle(precision):
+    specs, reqs = make_requests(40, qps=400.0, lo=1e3, hi=2e5, depth_lo=20, depth_hi=120, seed=31)
+    srv = qd().serve.Server(precision, budget_bytes=50e9, quantum=16, keep_states=True)
+    rep = srv.run(reqs, realtime=True)
+    assert rep["requests"] == 40 and rep["rejected"] == 0
+    assert rep["max_resident_requests"] > 1
+    for r, sp in zip(sorted(srv.finished, key=lambda r: r.rid), specs):
+        alone = qd().State(sp.spec.dims, precision)
+        alone.run_circuit(sp.spec.gates())
+        got = r.state.amplitudes()
+        assert np.array_equal(got, alone.amplitudes()), f"request {r.rid} differs from its solo run"
+        assert abs(r.norm - 1.0) < (1e-12 if precision == "c128" else 1e-4)
+        if sp.spec.D <= 20000:
+            assert_close(got, oracle.run(sp.spec.dims, sp.spec.gates()), precision, f"request {r.rid}")
+        alone.close()
+    srv.close()
+
+
+def test_budget_is_respected_and_oversized_rejected():
+    specs, reqs = make_requests(30, qps=1000.0, lo=1e4, hi=1e6, depth_lo=10, depth_hi=40, seed=32)
+    biggest = max(r.D for r in reqs) * 8
+    budget = 2.5 * biggest
+    huge = qd().serve.ServeRequest(999, 0.0, [7] * 11, qd().GateList([]))  # 1.98e9 amps: over the budget
+    srv = qd().serve.Server("c64", budget_bytes=budget, quantum=8)
+    rep = srv.run(reqs + [huge], realtime=True)
+    assert rep["rejected"] == 1 and huge.rejected
+    assert rep["requests"] == 30
+    assert srv.peak_bytes <= budget
+    srv.close()
+
+
+def test_arrivals_join_while_others_run():
+    # a long request arrives first; short ones arrive while it runs and must be
+    # admitted -- and finish -- before it does
+    specs, reqs = make_requests(12, qps=500.0, lo=1e3, hi=1e4, depth_lo=10, depth_hi=20, seed=33)
+    long_spec = circuits.CircuitSpec([2] * 26, 300, 77)
+    long_req = qd().serve.ServeRequest(100, 0.0, long_spec.dims, qd().GateList(long_spec.gates()))
+    for r in reqs:
+        r.arrival += 0.005
+    srv = qd().serve.Server("c64", quantum=4)
+    srv.run([long_req] + reqs, realtime=True)
+    shorts = [r for r in srv.finished if r.rid != 100]
+    assert all(r.admitted < long_req.finished for r in shorts)
+    assert sum(r.finished < long_req.finished for r in shorts) >= len(shorts) // 2
+    srv.close()
