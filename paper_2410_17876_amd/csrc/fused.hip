@@ -1,8 +1,9 @@
-// fused.hip - one HBM pass for a run of consecutive gates (fused.h explains
-// the tiling). One workgroup per tile: load the tile into LDS with non-temporal
-// loads of contiguous runs, apply each gate of the pass to the tile's classes
-// in order (the same per-class arithmetic as the one-gate sweeps, device.h),
-// write the tile back.
+// fused.hip - one HBM pass for a run of consecutive gates (fused.h explains the
+// tiling). One workgroup per tile: load the tile into LDS with non-temporal
+// loads of contiguous runs, apply each gate of the pass to the tile's classes in
+// order (the same per-class arithmetic as the one-gate sweeps, device.h), write
+// the tile back. fused_tile serves a single state, batch_tile one tile of one
+// (state, pass) item of a batched round.
 #include <hip/hip_runtime.h>
 
 #include "device.h"
@@ -24,23 +25,29 @@ constexpr int class_unroll() {
     return M <= 4 ? 4 : (M <= 8 ? 2 : 1);
 }
 
-template <typename R, int M>
+// Class base c of gate G inside the tile: from its table, or decoded.
+template <bool TABLE>
+__device__ __forceinline__ uint32_t class_base(const TileGate* __restrict__ G, const uint16_t* bases, uint32_t c) {
+    if constexpr (TABLE) return (uint32_t)bases[c];
+    else return decode_base<uint32_t>(G->dec, c);
+}
+
+template <typename R, int M, int BS, bool TABLE>
 __device__ __forceinline__ void tile_dense(typename Cx<R>::T* tile, const TileGate* __restrict__ G,
-                                           const typename Cx<R>::T* __restrict__ U,
-                                           const uint16_t* __restrict__ bases) {
+                                           const typename Cx<R>::T* __restrict__ U, const uint16_t* bases) {
     using T = typename Cx<R>::T;
     constexpr int UF = class_unroll<M>();
     uint32_t off[M];
 #pragma unroll
     for (int a = 0; a < M; ++a) off[a] = G->off[a];
     const uint32_t nc = G->n_classes;
-    for (uint32_t c0 = threadIdx.x; c0 < nc; c0 += UF * kFuseBlock) {
+    for (uint32_t c0 = threadIdx.x; c0 < nc; c0 += UF * BS) {
         uint32_t base[UF];
         bool ok[UF];
 #pragma unroll
         for (int u = 0; u < UF; ++u) {
-            ok[u] = c0 + u * kFuseBlock < nc;
-            base[u] = !ok[u] ? 0u : (bases ? bases[c0 + u * kFuseBlock] : decode_base<uint32_t>(G->dec, c0 + u * kFuseBlock));
+            ok[u] = c0 + u * BS < nc;
+            base[u] = class_base<TABLE>(G, bases, ok[u] ? c0 + u * BS : 0u);  // unconditional: no wait per load
         }
         T x[UF][M];
 #pragma unroll
@@ -59,17 +66,16 @@ __device__ __forceinline__ void tile_dense(typename Cx<R>::T* tile, const TileGa
                 // Rolled over rows: an unrolled M x M body lets the compiler hoist all
                 // of U out of the class loop into registers (spills for M > 4).
 #pragma unroll 1
-                for (int r = 0; r < M; ++r)
-                    tile[base[u] + off[r]] = dense_row<R, M>(x[u], [&](int i) { return U[i]; }, r);
+                for (int r = 0; r < M; ++r)  // G->off[r]: uniform, a scalar load (no stack copy of off)
+                    tile[base[u] + G->off[r]] = dense_row<R, M>(x[u], [&](int i) { return U[i]; }, r);
             }
         }
     }
 }
 
-template <typename R, int A>
+template <typename R, int A, int BS, bool TABLE>
 __device__ __forceinline__ void tile_mono(typename Cx<R>::T* tile, const TileGate* __restrict__ G,
-                                          const typename Cx<R>::T* __restrict__ lam,
-                                          const uint16_t* __restrict__ bases) {
+                                          const typename Cx<R>::T* __restrict__ lam, const uint16_t* bases) {
     using T = typename Cx<R>::T;
     constexpr int UF = class_unroll<A>();
     uint32_t src[A], dst[A];
@@ -80,13 +86,13 @@ __device__ __forceinline__ void tile_mono(typename Cx<R>::T* tile, const TileGat
     }
     const uint32_t nc = G->n_classes;
     const uint32_t mask = G->one_mask;
-    for (uint32_t c0 = threadIdx.x; c0 < nc; c0 += UF * kFuseBlock) {
+    for (uint32_t c0 = threadIdx.x; c0 < nc; c0 += UF * BS) {
         uint32_t base[UF];
         bool ok[UF];
 #pragma unroll
         for (int u = 0; u < UF; ++u) {
-            ok[u] = c0 + u * kFuseBlock < nc;
-            base[u] = !ok[u] ? 0u : (bases ? bases[c0 + u * kFuseBlock] : decode_base<uint32_t>(G->dec, c0 + u * kFuseBlock));
+            ok[u] = c0 + u * BS < nc;
+            base[u] = class_base<TABLE>(G, bases, ok[u] ? c0 + u * BS : 0u);  // unconditional: no wait per load
         }
         T x[UF][A];
 #pragma unroll
@@ -104,71 +110,24 @@ __device__ __forceinline__ void tile_mono(typename Cx<R>::T* tile, const TileGat
     }
 }
 
-// Geometry of one tile: `nchunks` wavefront-sized chunks of `runs` contiguous
-// runs of L amplitudes each.
-struct TileGeom {
-    uint32_t tile, L, chunks_per_run, nchunks;
-    FastDiv<uint32_t> cdiv;
-};
-
-// Tile <-> HBM. Each wavefront takes 64-amplitude chunks of runs; the run (and
-// its offset) is uniform per wavefront, so the only per-lane work is one add.
-template <typename T, typename I, bool LOAD>
-__device__ __forceinline__ void move_tile(T* __restrict__ psi, T* tile, I obase, const TileGeom& a,
-                                          const I* __restrict__ run_off) {
-    constexpr uint32_t nw = kFuseBlock / 64;
-    constexpr int U4 = 4;
-    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
-    const uint32_t lane = threadIdx.x % 64;
-    for (uint32_t k0 = wave; k0 < a.nchunks; k0 += U4 * nw) {
-        T v[U4];
-        uint32_t t_at[U4];
-        I g_at[U4];
-        bool ok[U4];
-#pragma unroll
-        for (int u = 0; u < U4; ++u) {
-            const uint32_t k = k0 + u * nw;
-            const uint32_t r = fast_div<uint32_t>(k, a.cdiv);  // uniform: scalar unit
-            const uint32_t e = (k - r * a.chunks_per_run) * 64 + lane;
-            ok[u] = k < a.nchunks && e < a.L;
-            t_at[u] = r * a.L + e;
-            g_at[u] = obase + (k < a.nchunks ? run_off[r] : (I)0) + (I)e;
-        }
-        if (LOAD) {
-#pragma unroll
-            for (int u = 0; u < U4; ++u)
-                if (ok[u]) v[u] = ld_stream(psi + g_at[u]);
-#pragma unroll
-            for (int u = 0; u < U4; ++u)
-                if (ok[u]) tile[t_at[u]] = v[u];
-        } else {
-#pragma unroll
-            for (int u = 0; u < U4; ++u)
-                if (ok[u]) st_stream(psi + g_at[u], tile[t_at[u]]);
-        }
-    }
-}
-
-// One tile of one fused pass: load, apply the pass's gates in order, store.
-template <typename R, typename I>
-__device__ __forceinline__ void process_tile(typename Cx<R>::T* __restrict__ psi, typename Cx<R>::T* tile, I obase,
-                                             const TileGeom& geo, int ngates, const TileGate* __restrict__ gates,
-                                             const unsigned char* __restrict__ blob,
-                                             const I* __restrict__ run_off) {
+// The pass's gates applied to an LDS-resident tile. With TABLE every gate's
+// class bases come from its uint16 table in the blob (bases_off), otherwise
+// they are decoded on the device.
+template <typename R, typename I, int BS, bool TABLE>
+__device__ __forceinline__ void apply_gates(typename Cx<R>::T* tile, I obase, int ngates,
+                                            const TileGate* __restrict__ gates,
+                                            const unsigned char* __restrict__ blob) {
     using T = typename Cx<R>::T;
-    move_tile<T, I, true>(psi, tile, obase, geo, run_off);
-    __syncthreads();
     for (int g = 0; g < ngates; ++g) {
         // g is uniform; say so, so that descriptor reads become scalar loads
         const TileGate* __restrict__ G = gates + __builtin_amdgcn_readfirstlane(g);
         if (G->n_outer > 0 && !outer_holds(G, (uint64_t)obase)) continue;  // uniform over the workgroup
         const T* U = reinterpret_cast<const T*>(blob + G->u_off);
-        const uint16_t* bases =
-            G->bases_off == kDecodeBases ? nullptr : reinterpret_cast<const uint16_t*>(blob + G->bases_off);
+        const uint16_t* bases = TABLE ? reinterpret_cast<const uint16_t*>(blob + G->bases_off) : nullptr;
         if (G->kind == kDense) {
             switch (G->M) {
 #define QD_DENSE_CASE(m) \
-    case m: tile_dense<R, m>(tile, G, U, bases); break;
+    case m: tile_dense<R, m, BS, TABLE>(tile, G, U, bases); break;
                 QD_DENSE_CASE(2) QD_DENSE_CASE(3) QD_DENSE_CASE(4) QD_DENSE_CASE(5) QD_DENSE_CASE(6)
                 QD_DENSE_CASE(7) QD_DENSE_CASE(8) QD_DENSE_CASE(9) QD_DENSE_CASE(10) QD_DENSE_CASE(11)
                 QD_DENSE_CASE(12) QD_DENSE_CASE(13) QD_DENSE_CASE(14) QD_DENSE_CASE(15) QD_DENSE_CASE(16)
@@ -178,7 +137,7 @@ __device__ __forceinline__ void process_tile(typename Cx<R>::T* __restrict__ psi
         } else {
             switch (G->M) {
 #define QD_MONO_CASE(m) \
-    case m: tile_mono<R, m>(tile, G, U, bases); break;
+    case m: tile_mono<R, m, BS, TABLE>(tile, G, U, bases); break;
                 QD_MONO_CASE(1) QD_MONO_CASE(2) QD_MONO_CASE(3) QD_MONO_CASE(4) QD_MONO_CASE(5) QD_MONO_CASE(6)
                 QD_MONO_CASE(7) QD_MONO_CASE(8) QD_MONO_CASE(9) QD_MONO_CASE(10) QD_MONO_CASE(11)
                 QD_MONO_CASE(12) QD_MONO_CASE(13) QD_MONO_CASE(14) QD_MONO_CASE(15) QD_MONO_CASE(16)
@@ -188,10 +147,65 @@ __device__ __forceinline__ void process_tile(typename Cx<R>::T* __restrict__ psi
         }
         __syncthreads();
     }
-    move_tile<T, I, false>(psi, tile, obase, geo, run_off);
 }
 
-template <typename R, typename I>
+// Geometry of one tile: `nchunks` wavefront-sized chunks of the tile's runs of
+// L contiguous amplitudes (chunk k: run k / chunks_per_run).
+struct TileGeom {
+    uint32_t tile, L, chunks_per_run, nchunks;
+    FastDiv<uint32_t> cdiv;
+};
+
+// Chunk k of the tile belongs to wavefront k % nw; the run (and its offset) is
+// uniform per wavefront, so the only per-lane work is one add. Out-of-range
+// chunks and lanes past the end of a run are clamped to the tile's last valid
+// element, so every address is in bounds and loads need no branch; the return
+// value says whether this lane's element is real.
+template <typename I>
+__device__ __forceinline__ bool chunk_at(const TileGeom& a, const I* __restrict__ run_off, uint32_t k, uint32_t lane,
+                                         uint32_t* t_at, I* g_off) {
+    const bool in = k < a.nchunks;
+    const uint32_t kk = in ? k : a.nchunks - 1;
+    const uint32_t r = fast_div<uint32_t>(kk, a.cdiv);  // uniform: scalar unit
+    const uint32_t e = (kk - r * a.chunks_per_run) * 64 + lane;
+    const uint32_t ec = e < a.L ? e : a.L - 1;
+    *t_at = r * a.L + ec;
+    *g_off = run_off[r] + (I)ec;
+    return in && e < a.L;
+}
+
+// Whole tile <-> HBM. Loads are unconditional (chunk_at clamps), so the
+// compiler issues a wavefront's U4 loads back to back with no wait between them:
+// 256 bytes per lane in flight, a whole 64 KB tile per 256-thread workgroup.
+template <typename T, typename I, bool LOAD, int BS>
+__device__ __forceinline__ void move_tile(T* __restrict__ psi, T* tile, I obase, const TileGeom& a,
+                                          const I* __restrict__ run_off) {
+    constexpr uint32_t nw = BS / 64;
+    constexpr int U4 = LOAD ? (int)(256 / sizeof(T)) : 4;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+    const uint32_t lane = threadIdx.x % 64;
+    for (uint32_t k0 = wave; k0 < a.nchunks; k0 += U4 * nw) {
+        T v[U4];
+        uint32_t t_at[U4];
+        I g_off[U4];
+        bool ok[U4];
+#pragma unroll
+        for (int u = 0; u < U4; ++u) ok[u] = chunk_at<I>(a, run_off, k0 + u * nw, lane, &t_at[u], &g_off[u]);
+        if (LOAD) {
+#pragma unroll
+            for (int u = 0; u < U4; ++u) v[u] = ld_stream(psi + obase + g_off[u]);
+#pragma unroll
+            for (int u = 0; u < U4; ++u)
+                if (ok[u]) tile[t_at[u]] = v[u];
+        } else {
+#pragma unroll
+            for (int u = 0; u < U4; ++u)
+                if (ok[u]) st_stream(psi + obase + g_off[u], tile[t_at[u]]);
+        }
+    }
+}
+
+template <typename R, typename I, bool TABLE>
 __global__ __launch_bounds__(kFuseBlock) void fused_tile(typename Cx<R>::T* __restrict__ psi, const FusedArgs<I> a,
                                                          const TileGate* __restrict__ gates,
                                                          const unsigned char* __restrict__ blob,
@@ -201,7 +215,10 @@ __global__ __launch_bounds__(kFuseBlock) void fused_tile(typename Cx<R>::T* __re
     T* tile = reinterpret_cast<T*>(smem_raw);
     const I obase = decode_base<I>(a.outer, (I)xcd_block());
     const TileGeom geo{a.tile, a.L, a.chunks_per_run, a.nchunks, a.cdiv};
-    process_tile<R, I>(psi, tile, obase, geo, a.ngates, gates, blob, run_off);
+    move_tile<T, I, true, kFuseBlock>(psi, tile, obase, geo, run_off);
+    __syncthreads();
+    apply_gates<R, I, kFuseBlock, TABLE>(tile, obase, a.ngates, gates, blob);
+    move_tile<T, I, false, kFuseBlock>(psi, tile, obase, geo, run_off);
 }
 
 // A batched round: workgroup b processes tile (b - first_block) of the item
@@ -222,9 +239,20 @@ __global__ __launch_bounds__(kFuseBlock) void batch_tile(const BatchItem* __rest
     const BatchItem* __restrict__ it = items + __builtin_amdgcn_readfirstlane(lo);
     const uint32_t obase = decode_base<uint32_t>(it->outer, b - it->first_block);
     const TileGeom geo{it->tile, it->L, it->chunks_per_run, it->nchunks, it->cdiv};
-    process_tile<R, uint32_t>(reinterpret_cast<T*>(it->psi), tile, obase, geo, it->ngates,
-                              reinterpret_cast<const TileGate*>(blob + it->gates_off), blob,
-                              reinterpret_cast<const uint32_t*>(blob + it->run_off_off));
+    T* psi = reinterpret_cast<T*>(it->psi);
+    const uint32_t* run_off = reinterpret_cast<const uint32_t*>(blob + it->run_off_off);
+    move_tile<T, uint32_t, true, kFuseBlock>(psi, tile, obase, geo, run_off);
+    __syncthreads();
+    apply_gates<R, uint32_t, kFuseBlock, false>(tile, obase, it->ngates,
+                                                reinterpret_cast<const TileGate*>(blob + it->gates_off), blob);
+    move_tile<T, uint32_t, false, kFuseBlock>(psi, tile, obase, geo, run_off);
+}
+
+template <typename K>
+static hipError_t allow_lds(K* kernel, size_t bytes) {
+    if (bytes <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)bytes);
 }
 
 template <typename R, typename I>
@@ -246,15 +274,20 @@ static hipError_t run_fused(const FusedLaunch& f, void* psi, const void* dblob, 
     a.cdiv = make_fast_div<uint32_t>(a.chunks_per_run);
     a.ngates = f.ngates;
     const unsigned char* b = static_cast<const unsigned char*>(dblob);
-    const size_t shmem = (size_t)f.tile * sizeof(T);
-    if (shmem > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fused_tile<R, I>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    const TileGate* tg = reinterpret_cast<const TileGate*>(b + f.gates_off);
+    const I* ro = reinterpret_cast<const I*>(b + f.run_off_off);
+    const size_t tile_bytes = (size_t)f.tile * sizeof(T);
+    if (f.tables) {
+        hipError_t e = allow_lds(fused_tile<R, I, true>, tile_bytes);
         if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((fused_tile<R, I, true>), dim3((unsigned)f.n_tiles), dim3(kFuseBlock), tile_bytes, st,
+                           static_cast<T*>(psi), a, tg, b, ro);
+    } else {
+        hipError_t e = allow_lds(fused_tile<R, I, false>, tile_bytes);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((fused_tile<R, I, false>), dim3((unsigned)f.n_tiles), dim3(kFuseBlock), tile_bytes, st,
+                           static_cast<T*>(psi), a, tg, b, ro);
     }
-    hipLaunchKernelGGL((fused_tile<R, I>), dim3((unsigned)f.n_tiles), dim3(kFuseBlock), shmem, st,
-                       static_cast<T*>(psi), a, reinterpret_cast<const TileGate*>(b + f.gates_off), b,
-                       reinterpret_cast<const I*>(b + f.run_off_off));
     return hipGetLastError();
 }
 
@@ -263,11 +296,8 @@ static hipError_t run_batch(const void* ditems, int nitems, uint32_t nblocks, ui
                             hipStream_t st) {
     using T = typename Cx<R>::T;
     const size_t shmem = (size_t)max_tile * sizeof(T);
-    if (shmem > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&batch_tile<R>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-        if (e != hipSuccess) return e;
-    }
+    hipError_t e = allow_lds(batch_tile<R>, shmem);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((batch_tile<R>), dim3(nblocks), dim3(kFuseBlock), shmem, st,
                        static_cast<const BatchItem*>(ditems), nitems, static_cast<const unsigned char*>(dblob));
     return hipGetLastError();

@@ -147,6 +147,7 @@ int build_fused(const int32_t* dims, int n, int precision, const CircuitGate* ga
     }
     delete gp;
     f.ngates = (int)tg.size();
+    f.tables = tables;
 
     // Blob: [TileGate x ngates][gate data][run offsets]. Descriptors' u_off are
     // relative to the start of the gate data; rebase them to the blob start.

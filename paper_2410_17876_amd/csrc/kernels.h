@@ -50,6 +50,7 @@ struct FusedLaunch {
     int ngates;
     size_t gates_off;
     size_t run_off_off;
+    bool tables;  // every gate ships its class-base table (else the kernel decodes class bases)
 };
 hipError_t launch_fused(const FusedLaunch& f, int precision, void* psi, const void* dblob, hipStream_t stream);
 

@@ -59,30 +59,39 @@ __global__ __launch_bounds__(kMfmaBlock) void block_mfma_c64(typename Cx<float>:
 #pragma unroll
     for (int s = 0; s < MP; ++s) a[s] = A[(size_t)(32 * rb + (lane & 31)) * K2 + 2 * s + (lane >> 5)];
     for (int i = threadIdx.x; i < MP; i += kMfmaBlock) offs[i] = i < M ? off[i] : (I)0;
+    // Wait for the fragments once, here: left to the compiler, the wait for them
+    // lands inside the tile loop, counted together with the prefetch loads, and
+    // the last MFMA of every tile then waits for the next tile's gather.
+    __builtin_amdgcn_s_waitcnt(0);
 
     auto ncols_of = [&](I t) -> int {
         const I left = dec.n_classes - t * (I)S::NT;
         return left < (I)S::NT ? (int)left : S::NT;
     };
     // Tile t's elements this thread gathers: element e = threadIdx.x + i * block,
-    // row r = e / NT (a class member), column c = e % NT (a class).
+    // row r = e / NT (a class member), column c = e % NT (a class). Padding rows
+    // and columns past the last class read element (0, 0) instead (in bounds,
+    // no branch, so the loads issue back to back) and stage as zeros.
     auto gather = [&](T (&v)[EPT], int buf, int ncols) {
+        I addr[EPT];
 #pragma unroll
         for (int i = 0; i < EPT; ++i) {
             const int e = threadIdx.x + i * kMfmaBlock;
             const int r = e / S::NT, c = e % S::NT;
-            v[i].x = 0.0f;
-            v[i].y = 0.0f;
-            if (r < M && c < ncols) v[i] = ld_stream(psi + bases[buf][c] + offs[r]);
+            const bool ok = r < M && c < ncols;
+            addr[i] = bases[buf][ok ? c : 0] + offs[ok ? r : 0];
         }
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) v[i] = ld_stream(psi + addr[i]);
     };
-    auto stage = [&](const T (&v)[EPT]) {
+    auto stage = [&](const T (&v)[EPT], int ncols) {
 #pragma unroll
         for (int i = 0; i < EPT; ++i) {
             const int e = threadIdx.x + i * kMfmaBlock;
             const int r = e / S::NT, c = e % S::NT;
-            Bs[r][c] = v[i].x;
-            Bs[MP + r][c] = v[i].y;
+            const bool ok = r < M && c < ncols;
+            Bs[r][c] = ok ? v[i].x : 0.0f;
+            Bs[MP + r][c] = ok ? v[i].y : 0.0f;
         }
     };
 
@@ -94,7 +103,7 @@ __global__ __launch_bounds__(kMfmaBlock) void block_mfma_c64(typename Cx<float>:
         __syncthreads();
         T v[EPT];
         gather(v, 0, nc);
-        stage(v);
+        stage(v, nc);
     }
     for (; t < ntiles; t += gridDim.x) {
         const int ncols = ncols_of(t);
@@ -131,7 +140,7 @@ __global__ __launch_bounds__(kMfmaBlock) void block_mfma_c64(typename Cx<float>:
             }
         }
         __syncthreads();  // Bs free
-        if (has_next) stage(pv);
+        if (has_next) stage(pv, ncols_next);
         cur ^= 1;
     }
 }
