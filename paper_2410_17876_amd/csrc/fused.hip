@@ -4,6 +4,11 @@
 // order (the same per-class arithmetic as the one-gate sweeps, device.h), write
 // the tile back. fused_tile serves a single state, batch_tile one tile of one
 // (state, pass) item of a batched round.
+//
+// Two workgroups share a CU (64 KB tiles), so one's loads and stores overlap the
+// other's LDS work. A persistent variant with one 512-thread workgroup per CU
+// that prefetched the next tile into registers measured slower (the LDS phase
+// then has no other workgroup to hide its latency) and was dropped.
 #include <hip/hip_runtime.h>
 
 #include "device.h"
@@ -111,19 +116,20 @@ __device__ __forceinline__ void tile_mono(typename Cx<R>::T* tile, const TileGat
 }
 
 // The pass's gates applied to an LDS-resident tile. With TABLE every gate's
-// class bases come from its uint16 table in the blob (bases_off), otherwise
-// they are decoded on the device.
+// class bases come from its uint16 table at tables + bases_off (tables is the
+// blob, or an LDS image of it shifted so that the same offsets apply),
+// otherwise they are decoded on the device.
 template <typename R, typename I, int BS, bool TABLE>
 __device__ __forceinline__ void apply_gates(typename Cx<R>::T* tile, I obase, int ngates,
                                             const TileGate* __restrict__ gates,
-                                            const unsigned char* __restrict__ blob) {
+                                            const unsigned char* __restrict__ blob, const unsigned char* tables) {
     using T = typename Cx<R>::T;
     for (int g = 0; g < ngates; ++g) {
         // g is uniform; say so, so that descriptor reads become scalar loads
         const TileGate* __restrict__ G = gates + __builtin_amdgcn_readfirstlane(g);
         if (G->n_outer > 0 && !outer_holds(G, (uint64_t)obase)) continue;  // uniform over the workgroup
         const T* U = reinterpret_cast<const T*>(blob + G->u_off);
-        const uint16_t* bases = TABLE ? reinterpret_cast<const uint16_t*>(blob + G->bases_off) : nullptr;
+        const uint16_t* bases = TABLE ? reinterpret_cast<const uint16_t*>(tables + G->bases_off) : nullptr;
         if (G->kind == kDense) {
             switch (G->M) {
 #define QD_DENSE_CASE(m) \
@@ -217,7 +223,7 @@ __global__ __launch_bounds__(kFuseBlock) void fused_tile(typename Cx<R>::T* __re
     const TileGeom geo{a.tile, a.L, a.chunks_per_run, a.nchunks, a.cdiv};
     move_tile<T, I, true, kFuseBlock>(psi, tile, obase, geo, run_off);
     __syncthreads();
-    apply_gates<R, I, kFuseBlock, TABLE>(tile, obase, a.ngates, gates, blob);
+    apply_gates<R, I, kFuseBlock, TABLE>(tile, obase, a.ngates, gates, blob, blob);
     move_tile<T, I, false, kFuseBlock>(psi, tile, obase, geo, run_off);
 }
 
@@ -244,7 +250,7 @@ __global__ __launch_bounds__(kFuseBlock) void batch_tile(const BatchItem* __rest
     move_tile<T, uint32_t, true, kFuseBlock>(psi, tile, obase, geo, run_off);
     __syncthreads();
     apply_gates<R, uint32_t, kFuseBlock, false>(tile, obase, it->ngates,
-                                                reinterpret_cast<const TileGate*>(blob + it->gates_off), blob);
+                                                reinterpret_cast<const TileGate*>(blob + it->gates_off), blob, blob);
     move_tile<T, uint32_t, false, kFuseBlock>(psi, tile, obase, geo, run_off);
 }
 
