@@ -48,6 +48,11 @@ class GateInfo(C.Structure):
 def _load() -> C.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run paper_2410_17876_amd/build.py (or __graft_entry__.build())")
+    # torch first: its bundled HIP runtime then satisfies libqd's libamdhip64
+    # dependency, so both share one runtime (and one device context). Loaded the
+    # other way round, the process holds two HIP runtimes, and the second one to
+    # initialise does not see the GPU.
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     i32p = C.POINTER(C.c_int32)
     f64p = C.POINTER(C.c_double)

@@ -138,9 +138,9 @@ int new_state(const int32_t* dims, int32_t n, int32_t precision, qd_state** out,
     s->D = *D;
     s->precision = precision;
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) {
+    if (hipError_t e = hipGetDevice(&dev); e != hipSuccess) {
         delete s;
-        return set_err(QD_ERR_DEVICE, "no HIP device available");
+        return set_err(QD_ERR_DEVICE, std::string("no HIP device available: ") + hipGetErrorString(e));
     }
     s->device = dev;
     *out = s;

@@ -27,7 +27,6 @@ constexpr int kTileMaxSeg = 8;      // free segments of a tile-local plan
 constexpr int kFuseMaxM = 16;       // class size (dense) / active count (monomial) inside a tile
 constexpr int kFuseMaxGates = 64;   // gates per fused pass
 constexpr int kMaxOuterCtl = 8;     // controls outside S per gate
-constexpr int kFuseBlock = 256;
 
 // A gate's classes inside a tile are the same for every tile. A single-state
 // pass ships their tile-local bases as a uint16 table (a tile has at most 32768

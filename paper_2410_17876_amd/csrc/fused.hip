@@ -187,7 +187,7 @@ template <typename T, typename I, bool LOAD, int BS>
 __device__ __forceinline__ void move_tile(T* __restrict__ psi, T* tile, I obase, const TileGeom& a,
                                           const I* __restrict__ run_off) {
     constexpr uint32_t nw = BS / 64;
-    constexpr int U4 = LOAD ? (int)(256 / sizeof(T)) : 4;
+    constexpr int U4 = LOAD ? (int)(65536 / (BS * sizeof(T))) : 4;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
     const uint32_t lane = threadIdx.x % 64;
     for (uint32_t k0 = wave; k0 < a.nchunks; k0 += U4 * nw) {
@@ -211,8 +211,16 @@ __device__ __forceinline__ void move_tile(T* __restrict__ psi, T* tile, I obase,
     }
 }
 
-template <typename R, typename I, bool TABLE>
-__global__ __launch_bounds__(kFuseBlock) void fused_tile(typename Cx<R>::T* __restrict__ psi, const FusedArgs<I> a,
+// Threads per tile workgroup. Two 64 KB tiles share a CU; complex64 runs eight
+// wavefronts per tile (16 per CU), complex128 four, since its larger registers
+// (131 VGPRs) do not fit four wavefronts per SIMD and capping them spills.
+template <typename R>
+constexpr int fuse_block() {
+    return sizeof(R) == 4 ? 512 : 256;
+}
+
+template <typename R, typename I, bool TABLE, int BS>
+__global__ __launch_bounds__(BS) void fused_tile(typename Cx<R>::T* __restrict__ psi, const FusedArgs<I> a,
                                                          const TileGate* __restrict__ gates,
                                                          const unsigned char* __restrict__ blob,
                                                          const I* __restrict__ run_off) {
@@ -221,16 +229,16 @@ __global__ __launch_bounds__(kFuseBlock) void fused_tile(typename Cx<R>::T* __re
     T* tile = reinterpret_cast<T*>(smem_raw);
     const I obase = decode_base<I>(a.outer, (I)xcd_block());
     const TileGeom geo{a.tile, a.L, a.chunks_per_run, a.nchunks, a.cdiv};
-    move_tile<T, I, true, kFuseBlock>(psi, tile, obase, geo, run_off);
+    move_tile<T, I, true, BS>(psi, tile, obase, geo, run_off);
     __syncthreads();
-    apply_gates<R, I, kFuseBlock, TABLE>(tile, obase, a.ngates, gates, blob, blob);
-    move_tile<T, I, false, kFuseBlock>(psi, tile, obase, geo, run_off);
+    apply_gates<R, I, BS, TABLE>(tile, obase, a.ngates, gates, blob, blob);
+    move_tile<T, I, false, BS>(psi, tile, obase, geo, run_off);
 }
 
 // A batched round: workgroup b processes tile (b - first_block) of the item
 // whose block range holds b (binary search over the items' first blocks).
-template <typename R>
-__global__ __launch_bounds__(kFuseBlock) void batch_tile(const BatchItem* __restrict__ items, int nitems,
+template <typename R, int BS>
+__global__ __launch_bounds__(BS) void batch_tile(const BatchItem* __restrict__ items, int nitems,
                                                          const unsigned char* __restrict__ blob) {
     using T = typename Cx<R>::T;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -247,11 +255,11 @@ __global__ __launch_bounds__(kFuseBlock) void batch_tile(const BatchItem* __rest
     const TileGeom geo{it->tile, it->L, it->chunks_per_run, it->nchunks, it->cdiv};
     T* psi = reinterpret_cast<T*>(it->psi);
     const uint32_t* run_off = reinterpret_cast<const uint32_t*>(blob + it->run_off_off);
-    move_tile<T, uint32_t, true, kFuseBlock>(psi, tile, obase, geo, run_off);
+    move_tile<T, uint32_t, true, BS>(psi, tile, obase, geo, run_off);
     __syncthreads();
-    apply_gates<R, uint32_t, kFuseBlock, false>(tile, obase, it->ngates,
-                                                reinterpret_cast<const TileGate*>(blob + it->gates_off), blob, blob);
-    move_tile<T, uint32_t, false, kFuseBlock>(psi, tile, obase, geo, run_off);
+    apply_gates<R, uint32_t, BS, false>(tile, obase, it->ngates,
+                                        reinterpret_cast<const TileGate*>(blob + it->gates_off), blob, blob);
+    move_tile<T, uint32_t, false, BS>(psi, tile, obase, geo, run_off);
 }
 
 template <typename K>
@@ -259,6 +267,14 @@ static hipError_t allow_lds(K* kernel, size_t bytes) {
     if (bytes <= 65536) return hipSuccess;
     return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)bytes);
+}
+
+template <auto K, typename... Args>
+static hipError_t launch_tile(const FusedLaunch& f, int bs, size_t shmem, hipStream_t st, Args... args) {
+    hipError_t e = allow_lds(K, shmem);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(K, dim3((unsigned)f.n_tiles), dim3(bs), shmem, st, args...);
+    return hipGetLastError();
 }
 
 template <typename R, typename I>
@@ -283,18 +299,9 @@ static hipError_t run_fused(const FusedLaunch& f, void* psi, const void* dblob, 
     const TileGate* tg = reinterpret_cast<const TileGate*>(b + f.gates_off);
     const I* ro = reinterpret_cast<const I*>(b + f.run_off_off);
     const size_t tile_bytes = (size_t)f.tile * sizeof(T);
-    if (f.tables) {
-        hipError_t e = allow_lds(fused_tile<R, I, true>, tile_bytes);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((fused_tile<R, I, true>), dim3((unsigned)f.n_tiles), dim3(kFuseBlock), tile_bytes, st,
-                           static_cast<T*>(psi), a, tg, b, ro);
-    } else {
-        hipError_t e = allow_lds(fused_tile<R, I, false>, tile_bytes);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((fused_tile<R, I, false>), dim3((unsigned)f.n_tiles), dim3(kFuseBlock), tile_bytes, st,
-                           static_cast<T*>(psi), a, tg, b, ro);
-    }
-    return hipGetLastError();
+    constexpr int BS = fuse_block<R>();
+    if (f.tables) return launch_tile<fused_tile<R, I, true, BS>>(f, BS, tile_bytes, st, static_cast<T*>(psi), a, tg, b, ro);
+    return launch_tile<fused_tile<R, I, false, BS>>(f, BS, tile_bytes, st, static_cast<T*>(psi), a, tg, b, ro);
 }
 
 template <typename R>
@@ -302,9 +309,10 @@ static hipError_t run_batch(const void* ditems, int nitems, uint32_t nblocks, ui
                             hipStream_t st) {
     using T = typename Cx<R>::T;
     const size_t shmem = (size_t)max_tile * sizeof(T);
-    hipError_t e = allow_lds(batch_tile<R>, shmem);
+    constexpr int BS = fuse_block<R>();
+    hipError_t e = allow_lds(batch_tile<R, BS>, shmem);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((batch_tile<R>), dim3(nblocks), dim3(kFuseBlock), shmem, st,
+    hipLaunchKernelGGL((batch_tile<R, BS>), dim3(nblocks), dim3(BS), shmem, st,
                        static_cast<const BatchItem*>(ditems), nitems, static_cast<const unsigned char*>(dblob));
     return hipGetLastError();
 }

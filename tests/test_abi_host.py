@@ -200,3 +200,17 @@ def test_batch_api_host_validation():
     assert lib.qd_batch_apply(h, None, None, None, 2, None) == -1
     assert lib.qd_batch_apply(None, None, None, None, 1, None) == -1
     assert lib.qd_batch_destroy(h) == 0
+
+
+def test_one_hip_runtime_whatever_the_import_order():
+    # The package loaded before torch must not bring in a second HIP runtime:
+    # the second runtime to initialise does not see the GPU.
+    import subprocess
+    import sys
+    code = ("import paper_2410_17876_amd, torch\n"
+            "libs = {l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}\n"
+            "print(len(libs))\n")
+    out = subprocess.run([sys.executable, "-c", code], cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                         capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"
