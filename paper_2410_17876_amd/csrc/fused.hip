@@ -30,6 +30,26 @@ constexpr int class_unroll() {
     return M <= 4 ? 4 : (M <= 8 ? 2 : 1);
 }
 
+// Class bases prefetched into registers: a thread's first kPre classes of a gate
+// (classes threadIdx.x + j * BS). With tables, a gate's bases are loaded while
+// the previous gate (or the tile load) is still in flight, so the per-gate
+// chain does not wait for them; the first 2 * UF classes of a thread come from
+// here, the rest (only for gates with more classes per thread) are loaded in
+// the class loop.
+constexpr int kPre = 8;
+
+template <int BS>
+__device__ __forceinline__ void prefetch_bases(const TileGate* __restrict__ G, const unsigned char* tables,
+                                               uint32_t (&pre)[kPre]) {
+    const uint16_t* bases = reinterpret_cast<const uint16_t*>(tables + G->bases_off);
+    const uint32_t nc = G->n_classes;
+#pragma unroll
+    for (int j = 0; j < kPre; ++j) {
+        const uint32_t c = threadIdx.x + j * BS;
+        pre[j] = bases[c < nc ? c : 0u];  // clamped: every load in bounds, none predicated
+    }
+}
+
 // Class base c of gate G inside the tile: from its table, or decoded.
 template <bool TABLE>
 __device__ __forceinline__ uint32_t class_base(const TileGate* __restrict__ G, const uint16_t* bases, uint32_t c) {
@@ -37,16 +57,78 @@ __device__ __forceinline__ uint32_t class_base(const TileGate* __restrict__ G, c
     else return decode_base<uint32_t>(G->dec, c);
 }
 
-template <typename R, int M, int BS, bool TABLE>
-__device__ __forceinline__ void tile_dense(typename Cx<R>::T* tile, const TileGate* __restrict__ G,
-                                           const typename Cx<R>::T* __restrict__ U, const uint16_t* bases) {
+// Dense update of UF classes (the same arithmetic as the one-gate sweep).
+template <typename R, int M, int UF>
+__device__ __forceinline__ void dense_classes(typename Cx<R>::T* tile, const TileGate* __restrict__ G,
+                                              const typename Cx<R>::T* __restrict__ U, const uint32_t (&off)[M],
+                                              const uint32_t (&base)[UF], const bool (&ok)[UF]) {
     using T = typename Cx<R>::T;
-    constexpr int UF = class_unroll<M>();
-    uint32_t off[M];
+    T x[UF][M];
 #pragma unroll
-    for (int a = 0; a < M; ++a) off[a] = G->off[a];
+    for (int u = 0; u < UF; ++u)
+#pragma unroll
+        for (int a = 0; a < M; ++a)
+            if (ok[u]) x[u][a] = tile[base[u] + off[a]];
+#pragma unroll
+    for (int u = 0; u < UF; ++u) {
+        if (!ok[u]) continue;
+        if constexpr (M <= 4) {
+#pragma unroll
+            for (int r = 0; r < M; ++r)
+                tile[base[u] + off[r]] = dense_row<R, M>(x[u], [&](int i) { return U[i]; }, r);
+        } else {
+            // Rolled over rows: an unrolled M x M body lets the compiler hoist all
+            // of U out of the class loop into registers (spills for M > 4).
+#pragma unroll 1
+            for (int r = 0; r < M; ++r)  // G->off[r]: uniform, a scalar load (no stack copy of off)
+                tile[base[u] + G->off[r]] = dense_row<R, M>(x[u], [&](int i) { return U[i]; }, r);
+        }
+    }
+}
+
+// Monomial update of UF classes: A active entries move (and scale) src -> dst.
+template <typename R, int A, int UF>
+__device__ __forceinline__ void mono_classes(typename Cx<R>::T* tile, const typename Cx<R>::T* __restrict__ lam,
+                                             const uint32_t (&src)[A], const uint32_t (&dst)[A], uint32_t mask,
+                                             const uint32_t (&base)[UF], const bool (&ok)[UF]) {
+    using T = typename Cx<R>::T;
+    T x[UF][A];
+#pragma unroll
+    for (int u = 0; u < UF; ++u)
+#pragma unroll
+        for (int i = 0; i < A; ++i)
+            if (ok[u]) x[u][i] = tile[base[u] + src[i]];
+#pragma unroll
+    for (int u = 0; u < UF; ++u) {
+        if (!ok[u]) continue;
+#pragma unroll
+        for (int i = 0; i < A; ++i)
+            tile[base[u] + dst[i]] = ((mask >> i) & 1u) ? x[u][i] : scale_by(lam[i], x[u][i]);
+    }
+}
+
+// A gate's classes, in trips of UF per thread. With TABLE the first 2 * UF
+// classes of the thread take their bases from pre (static indices, so pre stays
+// in registers), the rest from the table; without, every base is decoded.
+template <int UF, int BS, bool TABLE, typename Body>
+__device__ __forceinline__ void for_classes(const TileGate* __restrict__ G, const uint16_t* bases,
+                                            const uint32_t (&pre)[kPre], const Body& body) {
     const uint32_t nc = G->n_classes;
-    for (uint32_t c0 = threadIdx.x; c0 < nc; c0 += UF * BS) {
+    constexpr int P1 = TABLE ? 2 * UF : 0;
+    static_assert(P1 <= kPre, "prefetched classes exceed kPre");
+#pragma unroll
+    for (int t = 0; t < P1 / UF; ++t) {
+        if (threadIdx.x + (uint32_t)(t * UF) * BS >= nc) break;
+        uint32_t base[UF];
+        bool ok[UF];
+#pragma unroll
+        for (int u = 0; u < UF; ++u) {
+            ok[u] = threadIdx.x + (uint32_t)(t * UF + u) * BS < nc;
+            base[u] = pre[t * UF + u];
+        }
+        body(base, ok);
+    }
+    for (uint32_t c0 = threadIdx.x + (uint32_t)P1 * BS; c0 < nc; c0 += UF * BS) {
         uint32_t base[UF];
         bool ok[UF];
 #pragma unroll
@@ -54,34 +136,27 @@ __device__ __forceinline__ void tile_dense(typename Cx<R>::T* tile, const TileGa
             ok[u] = c0 + u * BS < nc;
             base[u] = class_base<TABLE>(G, bases, ok[u] ? c0 + u * BS : 0u);  // unconditional: no wait per load
         }
-        T x[UF][M];
-#pragma unroll
-        for (int u = 0; u < UF; ++u)
-#pragma unroll
-            for (int a = 0; a < M; ++a)
-                if (ok[u]) x[u][a] = tile[base[u] + off[a]];
-#pragma unroll
-        for (int u = 0; u < UF; ++u) {
-            if (!ok[u]) continue;
-            if constexpr (M <= 4) {
-#pragma unroll
-                for (int r = 0; r < M; ++r)
-                    tile[base[u] + off[r]] = dense_row<R, M>(x[u], [&](int i) { return U[i]; }, r);
-            } else {
-                // Rolled over rows: an unrolled M x M body lets the compiler hoist all
-                // of U out of the class loop into registers (spills for M > 4).
-#pragma unroll 1
-                for (int r = 0; r < M; ++r)  // G->off[r]: uniform, a scalar load (no stack copy of off)
-                    tile[base[u] + G->off[r]] = dense_row<R, M>(x[u], [&](int i) { return U[i]; }, r);
-            }
-        }
+        body(base, ok);
     }
+}
+
+template <typename R, int M, int BS, bool TABLE>
+__device__ __forceinline__ void tile_dense(typename Cx<R>::T* tile, const TileGate* __restrict__ G,
+                                           const typename Cx<R>::T* __restrict__ U, const uint16_t* bases,
+                                           const uint32_t (&pre)[kPre]) {
+    constexpr int UF = class_unroll<M>();
+    uint32_t off[M];
+#pragma unroll
+    for (int a = 0; a < M; ++a) off[a] = G->off[a];
+    for_classes<UF, BS, TABLE>(G, bases, pre, [&](const uint32_t (&base)[UF], const bool (&ok)[UF]) {
+        dense_classes<R, M, UF>(tile, G, U, off, base, ok);
+    });
 }
 
 template <typename R, int A, int BS, bool TABLE>
 __device__ __forceinline__ void tile_mono(typename Cx<R>::T* tile, const TileGate* __restrict__ G,
-                                          const typename Cx<R>::T* __restrict__ lam, const uint16_t* bases) {
-    using T = typename Cx<R>::T;
+                                          const typename Cx<R>::T* __restrict__ lam, const uint16_t* bases,
+                                          const uint32_t (&pre)[kPre]) {
     constexpr int UF = class_unroll<A>();
     uint32_t src[A], dst[A];
 #pragma unroll
@@ -89,51 +164,40 @@ __device__ __forceinline__ void tile_mono(typename Cx<R>::T* tile, const TileGat
         src[i] = G->off[i];
         dst[i] = G->dst[i];
     }
-    const uint32_t nc = G->n_classes;
     const uint32_t mask = G->one_mask;
-    for (uint32_t c0 = threadIdx.x; c0 < nc; c0 += UF * BS) {
-        uint32_t base[UF];
-        bool ok[UF];
-#pragma unroll
-        for (int u = 0; u < UF; ++u) {
-            ok[u] = c0 + u * BS < nc;
-            base[u] = class_base<TABLE>(G, bases, ok[u] ? c0 + u * BS : 0u);  // unconditional: no wait per load
-        }
-        T x[UF][A];
-#pragma unroll
-        for (int u = 0; u < UF; ++u)
-#pragma unroll
-            for (int i = 0; i < A; ++i)
-                if (ok[u]) x[u][i] = tile[base[u] + src[i]];
-#pragma unroll
-        for (int u = 0; u < UF; ++u) {
-            if (!ok[u]) continue;
-#pragma unroll
-            for (int i = 0; i < A; ++i)
-                tile[base[u] + dst[i]] = ((mask >> i) & 1u) ? x[u][i] : scale_by(lam[i], x[u][i]);
-        }
+    for_classes<UF, BS, TABLE>(G, bases, pre, [&](const uint32_t (&base)[UF], const bool (&ok)[UF]) {
+        mono_classes<R, A, UF>(tile, lam, src, dst, mask, base, ok);
+    });
+}
+
+// First gate at or after g whose outer controls hold for this tile (uniform).
+__device__ __forceinline__ int next_live_gate(const TileGate* __restrict__ gates, int g, int ngates, uint64_t obase) {
+    for (; g < ngates; ++g) {
+        const TileGate* __restrict__ G = gates + __builtin_amdgcn_readfirstlane(g);
+        if (G->n_outer == 0 || outer_holds(G, obase)) break;
     }
+    return g;
 }
 
 // The pass's gates applied to an LDS-resident tile. With TABLE every gate's
-// class bases come from its uint16 table at tables + bases_off (tables is the
-// blob, or an LDS image of it shifted so that the same offsets apply),
-// otherwise they are decoded on the device.
+// class bases come from its uint16 table at tables + bases_off, and pre holds
+// the prefetched bases of gate `first` (the first live gate, which the caller
+// prefetched); otherwise bases are decoded on the device and pre is unused.
 template <typename R, typename I, int BS, bool TABLE>
 __device__ __forceinline__ void apply_gates(typename Cx<R>::T* tile, I obase, int ngates,
                                             const TileGate* __restrict__ gates,
-                                            const unsigned char* __restrict__ blob, const unsigned char* tables) {
+                                            const unsigned char* __restrict__ blob, const unsigned char* tables,
+                                            int first, uint32_t (&pre)[kPre]) {
     using T = typename Cx<R>::T;
-    for (int g = 0; g < ngates; ++g) {
+    for (int g = first; g < ngates;) {
         // g is uniform; say so, so that descriptor reads become scalar loads
         const TileGate* __restrict__ G = gates + __builtin_amdgcn_readfirstlane(g);
-        if (G->n_outer > 0 && !outer_holds(G, (uint64_t)obase)) continue;  // uniform over the workgroup
         const T* U = reinterpret_cast<const T*>(blob + G->u_off);
         const uint16_t* bases = TABLE ? reinterpret_cast<const uint16_t*>(tables + G->bases_off) : nullptr;
         if (G->kind == kDense) {
             switch (G->M) {
 #define QD_DENSE_CASE(m) \
-    case m: tile_dense<R, m, BS, TABLE>(tile, G, U, bases); break;
+    case m: tile_dense<R, m, BS, TABLE>(tile, G, U, bases, pre); break;
                 QD_DENSE_CASE(2) QD_DENSE_CASE(3) QD_DENSE_CASE(4) QD_DENSE_CASE(5) QD_DENSE_CASE(6)
                 QD_DENSE_CASE(7) QD_DENSE_CASE(8) QD_DENSE_CASE(9) QD_DENSE_CASE(10) QD_DENSE_CASE(11)
                 QD_DENSE_CASE(12) QD_DENSE_CASE(13) QD_DENSE_CASE(14) QD_DENSE_CASE(15) QD_DENSE_CASE(16)
@@ -143,7 +207,7 @@ __device__ __forceinline__ void apply_gates(typename Cx<R>::T* tile, I obase, in
         } else {
             switch (G->M) {
 #define QD_MONO_CASE(m) \
-    case m: tile_mono<R, m, BS, TABLE>(tile, G, U, bases); break;
+    case m: tile_mono<R, m, BS, TABLE>(tile, G, U, bases, pre); break;
                 QD_MONO_CASE(1) QD_MONO_CASE(2) QD_MONO_CASE(3) QD_MONO_CASE(4) QD_MONO_CASE(5) QD_MONO_CASE(6)
                 QD_MONO_CASE(7) QD_MONO_CASE(8) QD_MONO_CASE(9) QD_MONO_CASE(10) QD_MONO_CASE(11)
                 QD_MONO_CASE(12) QD_MONO_CASE(13) QD_MONO_CASE(14) QD_MONO_CASE(15) QD_MONO_CASE(16)
@@ -151,6 +215,10 @@ __device__ __forceinline__ void apply_gates(typename Cx<R>::T* tile, I obase, in
                 default: break;
             }
         }
+        g = next_live_gate(gates, g + 1, ngates, (uint64_t)obase);
+        // The next gate's bases are loaded before the barrier: they depend on no
+        // tile data, and land while the slowest wavefront finishes this gate.
+        if (TABLE && g < ngates) prefetch_bases<BS>(gates + __builtin_amdgcn_readfirstlane(g), tables, pre);
         __syncthreads();
     }
 }
@@ -229,9 +297,13 @@ __global__ __launch_bounds__(BS) void fused_tile(typename Cx<R>::T* __restrict__
     T* tile = reinterpret_cast<T*>(smem_raw);
     const I obase = decode_base_rolled<I>(a.outer, (I)xcd_block());
     const TileGeom geo{a.tile, a.L, a.chunks_per_run, a.nchunks, a.cdiv};
+    const int first = next_live_gate(gates, 0, a.ngates, (uint64_t)obase);
+    uint32_t pre[kPre];
+    // The first gate's bases go out together with the tile's loads.
+    if (TABLE && first < a.ngates) prefetch_bases<BS>(gates + __builtin_amdgcn_readfirstlane(first), blob, pre);
     move_tile<T, I, true, BS>(psi, tile, obase, geo, run_off);
     __syncthreads();
-    apply_gates<R, I, BS, TABLE>(tile, obase, a.ngates, gates, blob, blob);
+    apply_gates<R, I, BS, TABLE>(tile, obase, a.ngates, gates, blob, blob, first, pre);
     move_tile<T, I, false, BS>(psi, tile, obase, geo, run_off);
 }
 
@@ -255,10 +327,12 @@ __global__ __launch_bounds__(BS) void batch_tile(const BatchItem* __restrict__ i
     const TileGeom geo{it->tile, it->L, it->chunks_per_run, it->nchunks, it->cdiv};
     T* psi = reinterpret_cast<T*>(it->psi);
     const uint32_t* run_off = reinterpret_cast<const uint32_t*>(blob + it->run_off_off);
+    const TileGate* __restrict__ gates = reinterpret_cast<const TileGate*>(blob + it->gates_off);
+    const int first = next_live_gate(gates, 0, it->ngates, (uint64_t)obase);
+    uint32_t pre[kPre];  // unused: batched passes decode class bases
     move_tile<T, uint32_t, true, BS>(psi, tile, obase, geo, run_off);
     __syncthreads();
-    apply_gates<R, uint32_t, BS, false>(tile, obase, it->ngates,
-                                        reinterpret_cast<const TileGate*>(blob + it->gates_off), blob, blob);
+    apply_gates<R, uint32_t, BS, false>(tile, obase, it->ngates, gates, blob, blob, first, pre);
     move_tile<T, uint32_t, false, BS>(psi, tile, obase, geo, run_off);
 }
 
