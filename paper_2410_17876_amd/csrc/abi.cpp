@@ -448,7 +448,7 @@ int qd_circuit_plan(const int32_t* dims, int32_t n, int32_t precision, const qd_
     if (rc) return set_err(rc, err);
     *npasses = (int32_t)plan.size();
     for (size_t i = 0; i < plan.size(); ++i) {
-        if (pass_gates) pass_gates[i] = plan[i].fused ? plan[i].launch.ngates : 1;
+        if (pass_gates) pass_gates[i] = (int32_t)plan[i].gates.size();
         if (pass_tile) pass_tile[i] = plan[i].fused ? (int32_t)plan[i].launch.tile : 0;
     }
     return QD_OK;

@@ -34,13 +34,25 @@ constexpr int kMaxOuterCtl = 8;     // controls outside S per gate
 // decodes them on the device instead (bases_off == kDecodeBases).
 constexpr uint32_t kDecodeBases = 0xffffffffu;
 
+// Two consecutive dense gates on disjoint targets, both with classes of at most
+// kPairMaxM amplitudes and no controls, share one descriptor: a thread reads the
+// joint class (the M1 x M2 amplitudes over both gates' targets, local index
+// a1 + M1 a2) from LDS once, applies the first gate to each of its M2 sub-classes
+// and the second to each of its M1 sub-classes in registers, and writes it back
+// once. Every amplitude sees the same operations as with the two gates applied
+// one after the other, so the result is bitwise the same, with half the LDS
+// traffic.
+constexpr int32_t kDensePair = 8;   // TileGate::kind of a pair (distinct from the Category values)
+constexpr int kPairMaxM = 4;
+
 struct TileGate {
-    int32_t kind;        // kDense, or kMonomial for monomial and diagonal gates
-    int32_t M;           // dense: class size; monomial: number of active entries
+    int32_t kind;        // kDense, kDensePair, or kMonomial for monomial and diagonal gates
+    int32_t M;           // dense: class size; pair: class size of the first gate; monomial: active entries
+    int32_t M2;          // pair: class size of the second gate (its U follows the first's in the blob)
     uint32_t n_classes;                 // classes of the gate inside one tile
     uint32_t bases_off;                 // byte offset of the uint16 class bases in the blob, or kDecodeBases
     Decode<uint32_t, kTileMaxSeg> dec;  // tile-local class decoder
-    uint32_t off[kFuseMaxM];            // dense: member offsets; monomial: source offsets
+    uint32_t off[kFuseMaxM];            // dense, pair: member offsets; monomial: source offsets
     uint32_t dst[kFuseMaxM];            // monomial: destination offsets
     uint32_t one_mask;                  // monomial: bit i set if factor i is exactly 1
     int32_t n_outer;                    // controls outside S

@@ -170,6 +170,59 @@ __device__ __forceinline__ void tile_mono(typename Cx<R>::T* tile, const TileGat
     });
 }
 
+// A dense pair (kDensePair in fused.h) on UF joint classes: the first gate on
+// each of the M2 sub-classes (local stride 1), then the second on each of the
+// M1 sub-classes (local stride M1), all in registers.
+template <typename R, int M1, int M2, int UF>
+__device__ __forceinline__ void pair_classes(typename Cx<R>::T* tile, const typename Cx<R>::T* __restrict__ U1,
+                                             const typename Cx<R>::T* __restrict__ U2, const uint32_t (&off)[M1 * M2],
+                                             const uint32_t (&base)[UF], const bool (&ok)[UF]) {
+    using T = typename Cx<R>::T;
+    constexpr int J = M1 * M2;
+    T x[UF][J];
+#pragma unroll
+    for (int u = 0; u < UF; ++u)
+#pragma unroll
+        for (int a = 0; a < J; ++a)
+            if (ok[u]) x[u][a] = tile[base[u] + off[a]];
+#pragma unroll
+    for (int u = 0; u < UF; ++u) {
+        if (!ok[u]) continue;
+#pragma unroll
+        for (int a2 = 0; a2 < M2; ++a2) {
+            T v[M1];
+#pragma unroll
+            for (int a = 0; a < M1; ++a) v[a] = x[u][a + M1 * a2];
+#pragma unroll
+            for (int r = 0; r < M1; ++r) x[u][r + M1 * a2] = dense_row<R, M1>(v, [&](int i) { return U1[i]; }, r);
+        }
+#pragma unroll
+        for (int a1 = 0; a1 < M1; ++a1) {
+            T v[M2];
+#pragma unroll
+            for (int b = 0; b < M2; ++b) v[b] = x[u][a1 + M1 * b];
+#pragma unroll
+            for (int r = 0; r < M2; ++r)
+                tile[base[u] + off[a1 + M1 * r]] = dense_row<R, M2>(v, [&](int i) { return U2[i]; }, r);
+        }
+    }
+}
+
+template <typename R, int M1, int M2, int BS, bool TABLE>
+__device__ __forceinline__ void tile_pair(typename Cx<R>::T* tile, const TileGate* __restrict__ G,
+                                          const typename Cx<R>::T* __restrict__ U, const uint16_t* bases,
+                                          const uint32_t (&pre)[kPre]) {
+    constexpr int J = M1 * M2;
+    constexpr int UF = class_unroll<J>();
+    uint32_t off[J];
+#pragma unroll
+    for (int a = 0; a < J; ++a) off[a] = G->off[a];
+    const typename Cx<R>::T* __restrict__ U2 = U + M1 * M1;  // the second gate's matrix follows the first's
+    for_classes<UF, BS, TABLE>(G, bases, pre, [&](const uint32_t (&base)[UF], const bool (&ok)[UF]) {
+        pair_classes<R, M1, M2, UF>(tile, U, U2, off, base, ok);
+    });
+}
+
 // First gate at or after g whose outer controls hold for this tile (uniform).
 __device__ __forceinline__ int next_live_gate(const TileGate* __restrict__ gates, int g, int ngates, uint64_t obase) {
     for (; g < ngates; ++g) {
@@ -194,7 +247,16 @@ __device__ __forceinline__ void apply_gates(typename Cx<R>::T* tile, I obase, in
         const TileGate* __restrict__ G = gates + __builtin_amdgcn_readfirstlane(g);
         const T* U = reinterpret_cast<const T*>(blob + G->u_off);
         const uint16_t* bases = TABLE ? reinterpret_cast<const uint16_t*>(tables + G->bases_off) : nullptr;
-        if (G->kind == kDense) {
+        if (G->kind == kDensePair) {
+            switch (G->M * 8 + G->M2) {
+#define QD_PAIR_CASE(m1, m2) \
+    case m1 * 8 + m2: tile_pair<R, m1, m2, BS, TABLE>(tile, G, U, bases, pre); break;
+                QD_PAIR_CASE(2, 2) QD_PAIR_CASE(2, 3) QD_PAIR_CASE(2, 4) QD_PAIR_CASE(3, 2) QD_PAIR_CASE(3, 3)
+                QD_PAIR_CASE(3, 4) QD_PAIR_CASE(4, 2) QD_PAIR_CASE(4, 3) QD_PAIR_CASE(4, 4)
+#undef QD_PAIR_CASE
+                default: break;
+            }
+        } else if (G->kind == kDense) {
             switch (G->M) {
 #define QD_DENSE_CASE(m) \
     case m: tile_dense<R, m, BS, TABLE>(tile, G, U, bases, pre); break;

@@ -76,14 +76,25 @@ int build_fused(const int32_t* dims, int n, int precision, const CircuitGate* ga
     const size_t ab = amp_bytes(precision);
     std::vector<TileGate> tg;
     std::vector<unsigned char> udata;
-    GatePlan* gp = new GatePlan;
+    // Tile-local plans of the pass's gates (identity gates dropped).
+    struct Local {
+        GatePlan plan;
+        TileGate t;
+        int k;
+        int32_t lt[QD_MAX_TARGETS];
+        int in_tile_controls;
+        int gi;
+    };
+    std::vector<Local> locs;
+    locs.reserve(idx.size());
     for (int gi : idx) {
         const CircuitGate& g = gates[gi];
-        int32_t lt[QD_MAX_TARGETS], lc[QD_MAX_CONTROLS], lv[QD_MAX_CONTROLS];
+        Local L;
+        std::memset(&L.t, 0, sizeof L.t);
+        int32_t lc[QD_MAX_CONTROLS], lv[QD_MAX_CONTROLS];
         int mi = 0;
-        TileGate t;
-        std::memset(&t, 0, sizeof t);
-        for (int l = 0; l < g.k; ++l) lt[l] = loc[g.targets[l]];
+        for (int l = 0; l < g.k; ++l) L.lt[l] = loc[g.targets[l]];
+        L.k = g.k;
         for (int l = 0; l < g.m; ++l) {
             const int c = g.controls[l];
             if (inS[c]) {
@@ -91,61 +102,109 @@ int build_fused(const int32_t* dims, int n, int precision, const CircuitGate* ga
                 lv[mi] = g.values[l];
                 ++mi;
             } else {
-                t.oc_stride[t.n_outer] = s[c];
-                t.oc_dim[t.n_outer] = (uint32_t)dims[c];
-                t.oc_val[t.n_outer] = (uint32_t)g.values[l];
-                ++t.n_outer;
+                L.t.oc_stride[L.t.n_outer] = s[c];
+                L.t.oc_dim[L.t.n_outer] = (uint32_t)dims[c];
+                L.t.oc_val[L.t.n_outer] = (uint32_t)g.values[l];
+                ++L.t.n_outer;
             }
         }
-        int rc = plan_gate(tdims, nS, lt, g.k, lc, lv, mi, g.U, gp, err);
-        if (rc) {
-            delete gp;
-            return rc;
-        }
-        if (gp->category == kIdentity) continue;
-        if (gp->nseg > kTileMaxSeg) {
-            delete gp;
+        L.in_tile_controls = mi;
+        L.gi = gi;
+        int rc = plan_gate(tdims, nS, L.lt, g.k, lc, lv, mi, g.U, &L.plan, err);
+        if (rc) return rc;
+        if (L.plan.category == kIdentity) continue;
+        if (L.plan.nseg > kTileMaxSeg) {
             *err = "tile-local plan has too many segments";
             return QD_ERR_NOT_SUPPORTED;
         }
-        t.n_classes = (uint32_t)gp->n_classes;
-        t.dec = make_decode<uint32_t, kTileMaxSeg>(*gp);
+        locs.push_back(std::move(L));
+    }
+    auto pairable = [&](const Local& A, const Local& B) {
+        if (A.plan.category != kDense || B.plan.category != kDense) return false;
+        if (A.in_tile_controls || B.in_tile_controls || A.t.n_outer || B.t.n_outer) return false;
+        if (A.plan.M > kPairMaxM || B.plan.M > kPairMaxM || A.k + B.k > QD_MAX_TARGETS) return false;
+        for (int i = 0; i < A.k; ++i)
+            for (int j = 0; j < B.k; ++j)
+                if (A.lt[i] == B.lt[j]) return false;
+        return true;
+    };
+    auto put_u = [&](const double* U, int M) {
+        const size_t at = udata.size();
+        udata.resize(at + (size_t)M * M * ab);
+        unsigned char* dst = udata.data() + at;
+        for (int i = 0; i < M * M; ++i) {
+            if (precision == kC128) put_complex<double>(dst + i * ab, U[2 * i], U[2 * i + 1]);
+            else put_complex<float>(dst + i * ab, U[2 * i], U[2 * i + 1]);
+        }
+    };
+    auto put_classes = [&](TileGate& t, const GatePlan& gp) {
+        t.n_classes = (uint32_t)gp.n_classes;
+        t.dec = make_decode<uint32_t, kTileMaxSeg>(gp);
         t.bases_off = kDecodeBases;
         if (tables) {  // tile-local class bases, decoded once here for every tile
             t.bases_off = (uint32_t)udata.size();
-            const Decode<uint64_t> dec = make_decode<uint64_t>(*gp);
-            udata.resize(align_up(udata.size() + 2 * (size_t)gp->n_classes, 16));
+            const Decode<uint64_t> dec = make_decode<uint64_t>(gp);
+            udata.resize(align_up(udata.size() + 2 * (size_t)gp.n_classes, 16));
             uint16_t* b = reinterpret_cast<uint16_t*>(udata.data() + t.bases_off);
-            for (uint64_t c = 0; c < gp->n_classes; ++c) b[c] = (uint16_t)decode_base<uint64_t>(dec, c);
+            for (uint64_t c = 0; c < gp.n_classes; ++c) b[c] = (uint16_t)decode_base<uint64_t>(dec, c);
         }
-        t.u_off = (uint32_t)udata.size();
-        if (gp->category == kDense) {
-            t.kind = kDense;
-            t.M = gp->M;
-            for (int a = 0; a < gp->M; ++a) t.off[a] = (uint32_t)gp->off[a];
-            udata.resize(udata.size() + (size_t)gp->M * gp->M * ab);
-            unsigned char* dst = udata.data() + t.u_off;
-            for (int i = 0; i < gp->M * gp->M; ++i) {
-                if (precision == kC128) put_complex<double>(dst + i * ab, g.U[2 * i], g.U[2 * i + 1]);
-                else put_complex<float>(dst + i * ab, g.U[2 * i], g.U[2 * i + 1]);
+    };
+    GatePlan joint;  // geometry of a pair's joint class
+    for (size_t i = 0; i < locs.size(); ++i) {
+        Local& A = locs[i];
+        TileGate t = A.t;
+        if (i + 1 < locs.size() && pairable(A, locs[i + 1])) {
+            // The joint class: targets of the first gate, then of the second (so the
+            // joint local index is a1 + M1 a2); U = identity, only the geometry is used.
+            const Local& B = locs[i + 1];
+            int32_t jt[QD_MAX_TARGETS];
+            for (int l = 0; l < A.k; ++l) jt[l] = A.lt[l];
+            for (int l = 0; l < B.k; ++l) jt[A.k + l] = B.lt[l];
+            const int J = A.plan.M * B.plan.M;
+            std::vector<double> eye(2 * (size_t)J * J, 0.0);
+            for (int a = 0; a < J; ++a) eye[2 * ((size_t)a * J + a)] = 1.0;
+            GatePlan& jp = joint;
+            int rc = plan_gate(tdims, nS, jt, A.k + B.k, nullptr, nullptr, 0, eye.data(), &jp, err);
+            if (rc) return rc;
+            if (jp.nseg > kTileMaxSeg) {
+                *err = "tile-local plan has too many segments";
+                return QD_ERR_NOT_SUPPORTED;
             }
+            put_classes(t, jp);
+            t.kind = kDensePair;
+            t.M = A.plan.M;
+            t.M2 = B.plan.M;
+            for (int a = 0; a < J; ++a) t.off[a] = (uint32_t)jp.off[a];
+            t.u_off = (uint32_t)udata.size();
+            put_u(gates[A.gi].U, A.plan.M);
+            put_u(gates[B.gi].U, B.plan.M);
+            ++i;
         } else {
-            t.kind = kMonomial;
-            t.M = gp->n_active;
-            udata.resize(udata.size() + (size_t)gp->n_active * ab);
-            unsigned char* dst = udata.data() + t.u_off;
-            for (int i = 0; i < gp->n_active; ++i) {
-                t.off[i] = (uint32_t)gp->off[gp->src[i]];
-                t.dst[i] = (uint32_t)gp->off[gp->dst[i]];
-                if (gp->lam_one[i]) t.one_mask |= 1u << i;
-                if (precision == kC128) put_complex<double>(dst + i * ab, gp->lam[2 * i], gp->lam[2 * i + 1]);
-                else put_complex<float>(dst + i * ab, gp->lam[2 * i], gp->lam[2 * i + 1]);
+            const GatePlan& gpl = A.plan;
+            put_classes(t, gpl);
+            t.u_off = (uint32_t)udata.size();
+            if (gpl.category == kDense) {
+                t.kind = kDense;
+                t.M = gpl.M;
+                for (int a = 0; a < gpl.M; ++a) t.off[a] = (uint32_t)gpl.off[a];
+                put_u(gates[A.gi].U, gpl.M);
+            } else {
+                t.kind = kMonomial;
+                t.M = gpl.n_active;
+                udata.resize(udata.size() + (size_t)gpl.n_active * ab);
+                unsigned char* dst = udata.data() + t.u_off;
+                for (int j = 0; j < gpl.n_active; ++j) {
+                    t.off[j] = (uint32_t)gpl.off[gpl.src[j]];
+                    t.dst[j] = (uint32_t)gpl.off[gpl.dst[j]];
+                    if (gpl.lam_one[j]) t.one_mask |= 1u << j;
+                    if (precision == kC128) put_complex<double>(dst + j * ab, gpl.lam[2 * j], gpl.lam[2 * j + 1]);
+                    else put_complex<float>(dst + j * ab, gpl.lam[2 * j], gpl.lam[2 * j + 1]);
+                }
             }
         }
         udata.resize(align_up(udata.size(), 16));
         tg.push_back(t);
     }
-    delete gp;
     f.ngates = (int)tg.size();
     f.tables = tables;
 

@@ -113,3 +113,40 @@ def test_large_tiles_and_errors():
     with pytest.raises(q.QDError):
         big.run_circuit(bad)
     assert np.array_equal(big.amplitudes(), before)
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_dense_pairs_bitwise(precision):
+    # Consecutive uncontrolled dense gates with classes of at most 4 amplitudes
+    # run two at a time in registers; every (M1, M2) in {2,3,4}^2 occurs, plus a
+    # 2-qubit gate followed by a 1-qudit gate. Fused, batched (device-decoded
+    # bases) and sequential results must agree bit for bit.
+    q = qd()
+    dims = [2, 3, 4, 2, 3, 2, 4, 2, 2, 3]
+    rng = np.random.default_rng(77)
+    by_dim = {d: [i for i, x in enumerate(dims) if x == d] for d in (2, 3, 4)}
+    gates = []
+    for _ in range(3):
+        for m1 in (2, 3, 4):
+            for m2 in (2, 3, 4):
+                q1 = int(rng.choice(by_dim[m1]))
+                q2 = int(rng.choice([x for x in by_dim[m2] if x != q1]))
+                gates += [Gate((q1,), haar(m1, rng)), Gate((q2,), haar(m2, rng))]
+    gates += [Gate((0, 3), haar(4, rng)), Gate((1,), haar(3, rng)), Gate((4,), dft(3)), Gate((2,), dft(4))]
+    psi0 = rand_state(rng, math.prod(dims))
+    tile = 4096 if precision == "c128" else 8192
+    fused = q.State(dims, precision, init=None).set_amplitudes(psi0)
+    fused.run_circuit(gates, tile_amps=tile, min_run=64)
+    seq = q.State(dims, precision, init=None).set_amplitudes(psi0)
+    seq.run(gates)
+    assert np.array_equal(fused.amplitudes(), seq.amplitudes())
+    runner = q.batch.BatchRunner([dims], precision)
+    runner.states[0].set_amplitudes(psi0)
+    runner.run([gates], tile_amps=tile, min_run=64)
+    assert np.array_equal(runner.states[0].amplitudes(), seq.amplitudes())
+    runner.close()
+    ref = psi0.copy() if precision == "c128" else (psi0.real.astype(np.float32).astype(np.float64) +
+                                                   1j * psi0.imag.astype(np.float32).astype(np.float64))
+    for g in gates:
+        oracle.apply_gate(dims, ref, g)
+    assert_close(fused.amplitudes(), ref, precision, "dense pairs")
