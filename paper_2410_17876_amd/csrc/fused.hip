@@ -69,19 +69,24 @@ __device__ __forceinline__ void dense_classes(typename Cx<R>::T* tile, const Til
 #pragma unroll
         for (int a = 0; a < M; ++a)
             if (ok[u]) x[u][a] = tile[base[u] + off[a]];
+    if constexpr (M <= 2) {
 #pragma unroll
-    for (int u = 0; u < UF; ++u) {
-        if (!ok[u]) continue;
-        if constexpr (M <= 4) {
+        for (int u = 0; u < UF; ++u) {
+            if (!ok[u]) continue;
 #pragma unroll
             for (int r = 0; r < M; ++r)
                 tile[base[u] + off[r]] = dense_row<R, M>(x[u], [&](int i) { return U[i]; }, r);
-        } else {
-            // Rolled over rows: an unrolled M x M body lets the compiler hoist all
-            // of U out of the class loop into registers (spills for M > 4).
+        }
+    } else {
+        // Rolled over rows, one row of U live at a time: unrolled, the compiler
+        // keeps all of U in scalar registers (4 M^2 of them in complex128), and
+        // the pressure spills the pass's other uniform state on every gate.
 #pragma unroll 1
-            for (int r = 0; r < M; ++r)  // G->off[r]: uniform, a scalar load (no stack copy of off)
-                tile[base[u] + G->off[r]] = dense_row<R, M>(x[u], [&](int i) { return U[i]; }, r);
+        for (int r = 0; r < M; ++r) {
+            const uint32_t o = G->off[r];  // uniform: a scalar load
+#pragma unroll
+            for (int u = 0; u < UF; ++u)
+                if (ok[u]) tile[base[u] + o] = dense_row<R, M>(x[u], [&](int i) { return U[i]; }, r);
         }
     }
 }
@@ -171,10 +176,11 @@ __device__ __forceinline__ void tile_mono(typename Cx<R>::T* tile, const TileGat
 }
 
 // A dense pair (kDensePair in fused.h) on UF joint classes: the first gate on
-// each of the M2 sub-classes (local stride 1), then the second on each of the
-// M1 sub-classes (local stride M1), all in registers.
+// each of the M2 sub-classes (local stride 1), the second on each of the M1
+// sub-classes (local stride M1), from registers.
 template <typename R, int M1, int M2, int UF>
-__device__ __forceinline__ void pair_classes(typename Cx<R>::T* tile, const typename Cx<R>::T* __restrict__ U1,
+__device__ __forceinline__ void pair_classes(typename Cx<R>::T* tile, const TileGate* __restrict__ G,
+                                             const typename Cx<R>::T* __restrict__ U1,
                                              const typename Cx<R>::T* __restrict__ U2, const uint32_t (&off)[M1 * M2],
                                              const uint32_t (&base)[UF], const bool (&ok)[UF]) {
     using T = typename Cx<R>::T;
@@ -185,25 +191,21 @@ __device__ __forceinline__ void pair_classes(typename Cx<R>::T* tile, const type
 #pragma unroll
         for (int a = 0; a < J; ++a)
             if (ok[u]) x[u][a] = tile[base[u] + off[a]];
+    // For each output row a1 of the first gate: y[b] = row a1 of U1 on sub-class
+    // b (x[M1 b .. M1 b + M1)), which is exactly the input of the second gate's
+    // sub-class a1; its rows go straight to LDS. Rolled loops keep one row of
+    // each matrix in scalar registers at a time.
+#pragma unroll 1
+    for (int a1 = 0; a1 < M1; ++a1) {
 #pragma unroll
-    for (int u = 0; u < UF; ++u) {
-        if (!ok[u]) continue;
+        for (int u = 0; u < UF; ++u) {
+            if (!ok[u]) continue;
+            T y[M2];
 #pragma unroll
-        for (int a2 = 0; a2 < M2; ++a2) {
-            T v[M1];
-#pragma unroll
-            for (int a = 0; a < M1; ++a) v[a] = x[u][a + M1 * a2];
-#pragma unroll
-            for (int r = 0; r < M1; ++r) x[u][r + M1 * a2] = dense_row<R, M1>(v, [&](int i) { return U1[i]; }, r);
-        }
-#pragma unroll
-        for (int a1 = 0; a1 < M1; ++a1) {
-            T v[M2];
-#pragma unroll
-            for (int b = 0; b < M2; ++b) v[b] = x[u][a1 + M1 * b];
-#pragma unroll
+            for (int b = 0; b < M2; ++b) y[b] = dense_row<R, M1>(&x[u][M1 * b], [&](int i) { return U1[i]; }, a1);
+#pragma unroll 1
             for (int r = 0; r < M2; ++r)
-                tile[base[u] + off[a1 + M1 * r]] = dense_row<R, M2>(v, [&](int i) { return U2[i]; }, r);
+                tile[base[u] + G->off[a1 + M1 * r]] = dense_row<R, M2>(y, [&](int i) { return U2[i]; }, r);
         }
     }
 }
@@ -219,7 +221,7 @@ __device__ __forceinline__ void tile_pair(typename Cx<R>::T* tile, const TileGat
     for (int a = 0; a < J; ++a) off[a] = G->off[a];
     const typename Cx<R>::T* __restrict__ U2 = U + M1 * M1;  // the second gate's matrix follows the first's
     for_classes<UF, BS, TABLE>(G, bases, pre, [&](const uint32_t (&base)[UF], const bool (&ok)[UF]) {
-        pair_classes<R, M1, M2, UF>(tile, U, U2, off, base, ok);
+        pair_classes<R, M1, M2, UF>(tile, G, U, U2, off, base, ok);
     });
 }
 
