@@ -33,23 +33,31 @@ __device__ __forceinline__ uint32_t xcd_block() {
     return x * q + (x < r ? x : r) + (b >> 3);
 }
 
-// Row r of U x for one class of M amplitudes. `u(i)` returns U's i-th entry
-// (row-major) already rounded to the working precision.
-template <typename R, int M, typename UGet>
-__device__ __forceinline__ typename Cx<R>::T dense_row(const typename Cx<R>::T* x, const UGet& u, int r) {
+// sum_a w(a) x[a] for one class of M amplitudes, ascending a, four real FMAs
+// per complex term. `w(a)` returns the a-th coefficient already rounded to the
+// working precision.
+template <typename R, int M, typename WGet>
+__device__ __forceinline__ typename Cx<R>::T dense_dot(const typename Cx<R>::T* x, const WGet& w) {
     R yr = 0, yi = 0;
 #pragma unroll
     for (int a = 0; a < M; ++a) {
-        const typename Cx<R>::T w = u(r * M + a);
-        yr = fma(w.x, x[a].x, yr);
-        yr = fma(-w.y, x[a].y, yr);
-        yi = fma(w.x, x[a].y, yi);
-        yi = fma(w.y, x[a].x, yi);
+        const typename Cx<R>::T c = w(a);
+        yr = fma(c.x, x[a].x, yr);
+        yr = fma(-c.y, x[a].y, yr);
+        yi = fma(c.x, x[a].y, yi);
+        yi = fma(c.y, x[a].x, yi);
     }
     typename Cx<R>::T y;
     y.x = yr;
     y.y = yi;
     return y;
+}
+
+// Row r of U x for one class of M amplitudes. `u(i)` returns U's i-th entry
+// (row-major) already rounded to the working precision.
+template <typename R, int M, typename UGet>
+__device__ __forceinline__ typename Cx<R>::T dense_row(const typename Cx<R>::T* x, const UGet& u, int r) {
+    return dense_dot<R, M>(x, [&](int a) { return u(r * M + a); });
 }
 
 // w * x for a monomial (phase / permutation) factor.

@@ -81,12 +81,32 @@ __device__ __forceinline__ void dense_classes(typename Cx<R>::T* tile, const Til
         // Rolled over rows, one row of U live at a time: unrolled, the compiler
         // keeps all of U in scalar registers (4 M^2 of them in complex128), and
         // the pressure spills the pass's other uniform state on every gate.
-#pragma unroll 1
-        for (int r = 0; r < M; ++r) {
-            const uint32_t o = G->off[r];  // uniform: a scalar load
+        if constexpr (M <= 4) {
+            // The next row's coefficients are loaded while this row is computed.
+            T w[M];
 #pragma unroll
-            for (int u = 0; u < UF; ++u)
-                if (ok[u]) tile[base[u] + o] = dense_row<R, M>(x[u], [&](int i) { return U[i]; }, r);
+            for (int a = 0; a < M; ++a) w[a] = U[a];
+#pragma unroll 1
+            for (int r = 0; r < M; ++r) {
+                const uint32_t o = G->off[r];  // uniform: a scalar load
+                T wn[M];
+                const int rn = r + 1 < M ? r + 1 : r;
+#pragma unroll
+                for (int a = 0; a < M; ++a) wn[a] = U[rn * M + a];
+#pragma unroll
+                for (int u = 0; u < UF; ++u)
+                    if (ok[u]) tile[base[u] + o] = dense_dot<R, M>(x[u], [&](int a) { return w[a]; });
+#pragma unroll
+                for (int a = 0; a < M; ++a) w[a] = wn[a];
+            }
+        } else {
+#pragma unroll 1
+            for (int r = 0; r < M; ++r) {
+                const uint32_t o = G->off[r];
+#pragma unroll
+                for (int u = 0; u < UF; ++u)
+                    if (ok[u]) tile[base[u] + o] = dense_row<R, M>(x[u], [&](int i) { return U[i]; }, r);
+            }
         }
     }
 }
@@ -193,19 +213,39 @@ __device__ __forceinline__ void pair_classes(typename Cx<R>::T* tile, const Tile
             if (ok[u]) x[u][a] = tile[base[u] + off[a]];
     // For each output row a1 of the first gate: y[b] = row a1 of U1 on sub-class
     // b (x[M1 b .. M1 b + M1)), which is exactly the input of the second gate's
-    // sub-class a1; its rows go straight to LDS. Rolled loops keep one row of
-    // each matrix in scalar registers at a time.
-#pragma unroll 1
-    for (int a1 = 0; a1 < M1; ++a1) {
+    // sub-class a1; its rows go straight to LDS.
+    if constexpr (M1 * M1 + M2 * M2 <= 8) {
+        // Two 2x2 matrices: all of both in scalar registers.
 #pragma unroll
-        for (int u = 0; u < UF; ++u) {
-            if (!ok[u]) continue;
-            T y[M2];
+        for (int a1 = 0; a1 < M1; ++a1)
 #pragma unroll
-            for (int b = 0; b < M2; ++b) y[b] = dense_row<R, M1>(&x[u][M1 * b], [&](int i) { return U1[i]; }, a1);
+            for (int u = 0; u < UF; ++u) {
+                if (!ok[u]) continue;
+                T y[M2];
+#pragma unroll
+                for (int b = 0; b < M2; ++b)
+                    y[b] = dense_row<R, M1>(&x[u][M1 * b], [&](int i) { return U1[i]; }, a1);
+#pragma unroll
+                for (int r = 0; r < M2; ++r)
+                    tile[base[u] + off[a1 + M1 * r]] = dense_row<R, M2>(y, [&](int i) { return U2[i]; }, r);
+            }
+    } else {
+        // Rolled loops keep one row of each matrix in scalar registers at a time.
 #pragma unroll 1
-            for (int r = 0; r < M2; ++r)
-                tile[base[u] + G->off[a1 + M1 * r]] = dense_row<R, M2>(y, [&](int i) { return U2[i]; }, r);
+        for (int a1 = 0; a1 < M1; ++a1) {
+            T w1[M1];
+#pragma unroll
+            for (int a = 0; a < M1; ++a) w1[a] = U1[a1 * M1 + a];
+#pragma unroll
+            for (int u = 0; u < UF; ++u) {
+                if (!ok[u]) continue;
+                T y[M2];
+#pragma unroll
+                for (int b = 0; b < M2; ++b) y[b] = dense_dot<R, M1>(&x[u][M1 * b], [&](int a) { return w1[a]; });
+#pragma unroll 1
+                for (int r = 0; r < M2; ++r)
+                    tile[base[u] + G->off[a1 + M1 * r]] = dense_row<R, M2>(y, [&](int i) { return U2[i]; }, r);
+            }
         }
     }
 }
