@@ -18,7 +18,19 @@
 // blocks back to LDS and scatters them to the classes' addresses. A tile's
 // classes are read completely before any of them is written, and tiles are
 // disjoint, so the update is in place.
+//
+// Gather and scatter walk a tile's elements in address order: when the lowest
+// qudits q0..q_{j-1} are all targets, their digits (the `inner` lowest address
+// digits, inner = their dims' product) vary fastest across lanes, then the
+// class, then the other targets' digits; rmap turns that order back into the
+// local index. Otherwise (inner = 1) lanes run over classes, whose lowest free
+// digit is q0. Either way a wavefront touches contiguous amplitudes (walking
+// the classes first with q0 a target would stride the lanes by d0 amplitudes
+// and cost up to 10x on the low-target gates).
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
 
 #include "device.h"
 #include "kernels.h"
@@ -35,20 +47,27 @@ struct MfmaShape {
     static constexpr int RB = 2 * MP / 32;  // 32-row blocks of the real matrix
     static constexpr int NB = 8 / RB;       // 32-column blocks per tile
     static constexpr int NT = 32 * NB;      // columns (classes) per tile
+    static constexpr int LOG_NT = NT == 128 ? 7 : (NT == 64 ? 6 : 5);
 };
 
 template <int MP, typename I>
 __global__ __launch_bounds__(kMfmaBlock) void block_mfma_c64(typename Cx<float>::T* __restrict__ psi,
                                                              const Decode<I> dec, const int M, const I ntiles,
                                                              const float* __restrict__ A,
-                                                             const I* __restrict__ off) {
+                                                             const I* __restrict__ off,
+                                                             const int32_t* __restrict__ rmap_g, const int inner,
+                                                             const FastDiv<uint32_t> idiv) {
     using T = typename Cx<float>::T;
     using S = MfmaShape<MP>;
     constexpr int K2 = 2 * MP;
     constexpr int EPT = MP * S::NT / kMfmaBlock;  // tile elements gathered per thread
-    __shared__ float Bs[K2][S::NT];  // 32 KB: real rows 0..MP-1, imaginary rows MP..2MP-1
+    // 33 KB: real rows 0..MP-1, imaginary rows MP..2MP-1. One padding column, so
+    // that a wavefront writing down a column (low targets: consecutive lanes,
+    // consecutive rows) hits distinct banks.
+    __shared__ float Bs[K2][S::NT + 1];
     __shared__ I bases[2][S::NT];    // class bases of the current and the next tile
     __shared__ I offs[MP];
+    __shared__ int32_t rmap[MP];
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -58,7 +77,15 @@ __global__ __launch_bounds__(kMfmaBlock) void block_mfma_c64(typename Cx<float>:
     float a[MP];
 #pragma unroll
     for (int s = 0; s < MP; ++s) a[s] = A[(size_t)(32 * rb + (lane & 31)) * K2 + 2 * s + (lane >> 5)];
-    for (int i = threadIdx.x; i < MP; i += kMfmaBlock) offs[i] = i < M ? off[i] : (I)0;
+    for (int i = threadIdx.x; i < MP; i += kMfmaBlock) {
+        offs[i] = i < M ? off[i] : (I)0;
+        rmap[i] = i < M ? rmap_g[i] : 0;
+    }
+    // Padding rows (M..MP-1) of the B tile are never gathered: zero them once
+    // (the MFMA multiplies them by A's zero columns; they must be finite). The
+    // write-back of the result keeps them zero (A's padding rows are zero).
+    for (int i = threadIdx.x; i < K2 * (S::NT + 1); i += kMfmaBlock) (&Bs[0][0])[i] = 0.0f;
+    __syncthreads();
     // Wait for the fragments once, here: left to the compiler, the wait for them
     // lands inside the tile loop, counted together with the prefetch loads, and
     // the last MFMA of every tile then waits for the next tile's gather.
@@ -68,17 +95,31 @@ __global__ __launch_bounds__(kMfmaBlock) void block_mfma_c64(typename Cx<float>:
         const I left = dec.n_classes - t * (I)S::NT;
         return left < (I)S::NT ? (int)left : S::NT;
     };
-    // Tile t's elements this thread gathers: element e = threadIdx.x + i * block,
-    // row r = e / NT (a class member), column c = e % NT (a class). Padding rows
-    // and columns past the last class read element (0, 0) instead (in bounds,
-    // no branch, so the loads issue back to back) and stage as zeros.
+    // Element e of a tile in address order: low = e mod inner (the low target
+    // digits), then the class c, then hi (the other target digits); r is the
+    // local index. Elements e >= M * NT do not exist; c >= ncols is past the
+    // last class. Such elements load element (0, 0) (in bounds, no branch, so
+    // the loads issue back to back) and are neither staged nor stored.
+    const int MN = M * S::NT;
+    auto element = [&](int e, int ncols, int* r, int* c) -> bool {
+        if (inner == 1) {  // uniform: lanes over classes, then members
+            *c = e & (S::NT - 1);
+            *r = e >> S::LOG_NT;
+            return e < MN && *c < ncols;
+        }
+        const uint32_t q = fast_div<uint32_t>((uint32_t)e, idiv);
+        const int low = e - (int)q * inner;
+        const bool real = e < MN;
+        *c = (int)(q & (S::NT - 1));
+        *r = rmap[real ? low + inner * (int)(q >> S::LOG_NT) : 0];  // index < M for real elements
+        return real && *c < ncols;
+    };
     auto gather = [&](T (&v)[EPT], int buf, int ncols) {
         I addr[EPT];
 #pragma unroll
         for (int i = 0; i < EPT; ++i) {
-            const int e = threadIdx.x + i * kMfmaBlock;
-            const int r = e / S::NT, c = e % S::NT;
-            const bool ok = r < M && c < ncols;
+            int r = 0, c = 0;
+            const bool ok = element(threadIdx.x + i * kMfmaBlock, ncols, &r, &c);
             addr[i] = bases[buf][ok ? c : 0] + offs[ok ? r : 0];
         }
 #pragma unroll
@@ -87,11 +128,11 @@ __global__ __launch_bounds__(kMfmaBlock) void block_mfma_c64(typename Cx<float>:
     auto stage = [&](const T (&v)[EPT], int ncols) {
 #pragma unroll
         for (int i = 0; i < EPT; ++i) {
-            const int e = threadIdx.x + i * kMfmaBlock;
-            const int r = e / S::NT, c = e % S::NT;
-            const bool ok = r < M && c < ncols;
-            Bs[r][c] = ok ? v[i].x : 0.0f;
-            Bs[MP + r][c] = ok ? v[i].y : 0.0f;
+            int r = 0, c = 0;
+            if (element(threadIdx.x + i * kMfmaBlock, ncols, &r, &c)) {
+                Bs[r][c] = v[i].x;
+                Bs[MP + r][c] = v[i].y;
+            }
         }
     };
 
@@ -130,9 +171,9 @@ __global__ __launch_bounds__(kMfmaBlock) void block_mfma_c64(typename Cx<float>:
         for (int r = 0; r < 16; ++r)
             Bs[32 * rb + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)][32 * cb + (lane & 31)] = acc[r];
         __syncthreads();
-        for (int e = threadIdx.x; e < MP * S::NT; e += kMfmaBlock) {
-            const int r = e / S::NT, c = e % S::NT;
-            if (r < M && c < ncols) {
+        for (int e = threadIdx.x; e < MN; e += kMfmaBlock) {
+            int r = 0, c = 0;
+            if (element(e, ncols, &r, &c)) {
                 T y;
                 y.x = Bs[r][c];
                 y.y = Bs[MP + r][c];
@@ -149,7 +190,32 @@ int mfma_padded(int M) { return M <= 32 ? 32 : (M <= 64 ? 64 : 128); }
 
 size_t mfma_gate_bytes(int M, bool narrow) {
     const size_t K2 = 2 * (size_t)mfma_padded(M);
-    return K2 * K2 * sizeof(float) + (size_t)M * (narrow ? 4 : 8);
+    return K2 * K2 * sizeof(float) + (size_t)M * (narrow ? 4 : 8) + (size_t)M * 4;
+}
+
+// The address-order map of the gather (see the header): inner = the largest m
+// such that the member offsets include 0..m-1 (the lowest qudits are targets up
+// to that product), and rmap[low + inner * hi] = the local index whose offset is
+// low plus the hi-th smallest multiple of inner among the offsets.
+static int mfma_inner(const GatePlan& p) {
+    std::vector<bool> has(p.M + 1, false);
+    for (int a = 0; a < p.M; ++a)
+        if (p.off[a] >= 0 && p.off[a] <= p.M) has[(size_t)p.off[a]] = true;
+    int m = 0;
+    while (m < p.M && has[(size_t)m]) ++m;
+    return m < 1 ? 1 : m;
+}
+
+static void mfma_rmap(const GatePlan& p, int inner, int32_t* rmap) {
+    std::vector<int64_t> his;
+    for (int a = 0; a < p.M; ++a) his.push_back(p.off[a] - p.off[a] % inner);
+    std::sort(his.begin(), his.end());
+    his.erase(std::unique(his.begin(), his.end()), his.end());
+    for (int a = 0; a < p.M; ++a) {
+        const int64_t low = p.off[a] % inner;
+        const int64_t hi = std::lower_bound(his.begin(), his.end(), p.off[a] - low) - his.begin();
+        rmap[low + (int64_t)inner * hi] = a;
+    }
 }
 
 void fill_mfma_gate(const GatePlan& p, const double* U, void* dst) {
@@ -167,13 +233,16 @@ void fill_mfma_gate(const GatePlan& p, const double* U, void* dst) {
             A[(MP + r) * K2 + MP + c] = ur;
         }
     unsigned char* o = static_cast<unsigned char*>(dst) + (size_t)K2 * K2 * sizeof(float);
-    if (p.D < (1ull << 31)) {
+    const bool narrow = p.D < (1ull << 31);
+    if (narrow) {
         uint32_t* oo = reinterpret_cast<uint32_t*>(o);
         for (int a = 0; a < p.M; ++a) oo[a] = (uint32_t)p.off[a];
     } else {
         uint64_t* oo = reinterpret_cast<uint64_t*>(o);
         for (int a = 0; a < p.M; ++a) oo[a] = (uint64_t)p.off[a];
     }
+    int32_t* rm = reinterpret_cast<int32_t*>(o + (size_t)p.M * (narrow ? 4 : 8));
+    mfma_rmap(p, mfma_inner(p), rm);
 }
 
 template <int MP, typename I>
@@ -196,8 +265,11 @@ static hipError_t run_mfma(const GatePlan& p, void* psi, const void* dgate, hipS
     const float* A = static_cast<const float*>(dgate);
     const I* off = reinterpret_cast<const I*>(static_cast<const unsigned char*>(dgate) +
                                               (size_t)(2 * MP) * (2 * MP) * sizeof(float));
+    const int32_t* rmap = reinterpret_cast<const int32_t*>(off + p.M);
+    const int inner = mfma_inner(p);
     hipLaunchKernelGGL((block_mfma_c64<MP, I>), dim3((unsigned)grid), dim3(kMfmaBlock), 0, st,
-                       static_cast<typename Cx<float>::T*>(psi), dec, p.M, (I)ntiles, A, off);
+                       static_cast<typename Cx<float>::T*>(psi), dec, p.M, (I)ntiles, A, off, rmap, inner,
+                       make_fast_div<uint32_t>((uint64_t)inner));
     return hipGetLastError();
 }
 
