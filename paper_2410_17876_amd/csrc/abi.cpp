@@ -603,8 +603,11 @@ struct BatchInput {
     size_t rounds = 0;
 };
 
+// tables: ship each tile gate's class-base table (worth it for compiled plans,
+// uploaded once; eager rounds decode on the device to keep uploads small).
 int batch_validate_and_plan(int precision, qd_state* const* states, const qd_gate_desc* const* gates,
-                            const int32_t* counts, int32_t nstates, const qd_circuit_options* opts, BatchInput& in) {
+                            const int32_t* counts, int32_t nstates, const qd_circuit_options* opts, bool tables,
+                            BatchInput& in) {
     if (nstates < 0) return set_err(QD_ERR_INVALID_ARGUMENT, "negative state count");
     if (nstates > 0 && (!states || !gates || !counts))
         return set_err(QD_ERR_INVALID_ARGUMENT, "states, gates or counts is null");
@@ -627,7 +630,7 @@ int batch_validate_and_plan(int precision, qd_state* const* states, const qd_gat
     int rc = circuit_options(opts, precision, &co);
     if (rc) return rc;
     co.fuse = true;
-    co.tables = false;
+    co.tables = tables;
     co.single_as_fused = true;
     in.plans.assign(nstates, {});
     in.rounds = 0;
@@ -743,7 +746,7 @@ int qd_batch_apply(qd_batch* b, qd_state* const* states, const qd_gate_desc* con
     if (!b) return set_err(QD_ERR_INVALID_ARGUMENT, "batch is null");
     if (nstates == 0) return QD_OK;
     BatchInput in;
-    int rc = batch_validate_and_plan(b->precision, states, gates, counts, nstates, opts, in);
+    int rc = batch_validate_and_plan(b->precision, states, gates, counts, nstates, opts, false, in);
     if (rc) return rc;
     qd_state* s0 = states[0];
     rc = use_device(s0);
@@ -760,7 +763,7 @@ int qd_batch_apply(qd_batch* b, qd_state* const* states, const qd_gate_desc* con
             const unsigned char* dblob = nullptr;
             rc = batch_stage(b, hr.blob, st, &dblob);
             if (rc) return rc;
-            QD_HIP(launch_batch(b->precision, dblob + hr.items_off, hr.nitems, (uint32_t)hr.nblocks, hr.max_tile,
+            QD_HIP(launch_batch(b->precision, false, dblob + hr.items_off, hr.nitems, (uint32_t)hr.nblocks, hr.max_tile,
                                 dblob, st),
                    "batch launch");
             items_total += hr.nitems;
@@ -784,7 +787,7 @@ int qd_batch_compile(qd_state* const* states, const qd_gate_desc* const* gates, 
     if (nstates < 1 || !states || !states[0]) return set_err(QD_ERR_INVALID_ARGUMENT, "a plan needs at least one state");
     const int precision = states[0]->precision;
     BatchInput in;
-    int rc = batch_validate_and_plan(precision, states, gates, counts, nstates, opts, in);
+    int rc = batch_validate_and_plan(precision, states, gates, counts, nstates, opts, true, in);
     if (rc) return rc;
     qd_batch_plan* P = new qd_batch_plan();
     P->precision = precision;
@@ -839,7 +842,8 @@ namespace {
 hipError_t plan_enqueue(qd_batch_plan* P, hipStream_t st) {
     for (const auto& R : P->rounds) {
         if (!R.nitems) continue;
-        hipError_t e = launch_batch(P->precision, P->dev + R.blob_off + R.items_off, R.nitems, R.nblocks, R.max_tile,
+        hipError_t e = launch_batch(P->precision, true, P->dev + R.blob_off + R.items_off, R.nitems, R.nblocks,
+                                    R.max_tile,
                                     P->dev + R.blob_off, st);
         if (e != hipSuccess) return e;
     }

@@ -413,7 +413,7 @@ __global__ __launch_bounds__(BS) void fused_tile(typename Cx<R>::T* __restrict__
 
 // A batched round: workgroup b processes tile (b - first_block) of the item
 // whose block range holds b (binary search over the items' first blocks).
-template <typename R, int BS>
+template <typename R, int BS, bool TABLE>
 __global__ __launch_bounds__(BS) void batch_tile(const BatchItem* __restrict__ items, int nitems,
                                                          const unsigned char* __restrict__ blob) {
     using T = typename Cx<R>::T;
@@ -433,10 +433,11 @@ __global__ __launch_bounds__(BS) void batch_tile(const BatchItem* __restrict__ i
     const uint32_t* run_off = reinterpret_cast<const uint32_t*>(blob + it->run_off_off);
     const TileGate* __restrict__ gates = reinterpret_cast<const TileGate*>(blob + it->gates_off);
     const int first = next_live_gate(gates, 0, it->ngates, (uint64_t)obase);
-    uint32_t pre[kPre];  // unused: batched passes decode class bases
+    uint32_t pre[kPre];
+    if (TABLE && first < it->ngates) prefetch_bases<BS>(gates + __builtin_amdgcn_readfirstlane(first), blob, pre);
     move_tile<T, uint32_t, true, BS>(psi, tile, obase, geo, run_off);
     __syncthreads();
-    apply_gates<R, uint32_t, BS, false>(tile, obase, it->ngates, gates, blob, blob, first, pre);
+    apply_gates<R, uint32_t, BS, TABLE>(tile, obase, it->ngates, gates, blob, blob, first, pre);
     move_tile<T, uint32_t, false, BS>(psi, tile, obase, geo, run_off);
 }
 
@@ -482,25 +483,28 @@ static hipError_t run_fused(const FusedLaunch& f, void* psi, const void* dblob, 
     return launch_tile<fused_tile<R, I, false, BS>>(f, BS, tile_bytes, st, static_cast<T*>(psi), a, tg, b, ro);
 }
 
-template <typename R>
+template <typename R, bool TABLE>
 static hipError_t run_batch(const void* ditems, int nitems, uint32_t nblocks, uint32_t max_tile, const void* dblob,
                             hipStream_t st) {
     using T = typename Cx<R>::T;
     const size_t shmem = (size_t)max_tile * sizeof(T);
     constexpr int BS = fuse_block<R>();
-    hipError_t e = allow_lds(batch_tile<R, BS>, shmem);
+    hipError_t e = allow_lds(batch_tile<R, BS, TABLE>, shmem);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((batch_tile<R, BS>), dim3(nblocks), dim3(BS), shmem, st,
+    hipLaunchKernelGGL((batch_tile<R, BS, TABLE>), dim3(nblocks), dim3(BS), shmem, st,
                        static_cast<const BatchItem*>(ditems), nitems, static_cast<const unsigned char*>(dblob));
     return hipGetLastError();
 }
 
-hipError_t launch_batch(int precision, const void* ditems, int nitems, uint32_t nblocks, uint32_t max_tile,
-                        const void* dblob, hipStream_t st) {
+hipError_t launch_batch(int precision, bool tables, const void* ditems, int nitems, uint32_t nblocks,
+                        uint32_t max_tile, const void* dblob, hipStream_t st) {
     if (nitems <= 0 || nblocks == 0) return hipSuccess;
     if (nblocks > 0x7fffffffu) return hipErrorInvalidValue;
-    return precision == kC128 ? run_batch<double>(ditems, nitems, nblocks, max_tile, dblob, st)
-                              : run_batch<float>(ditems, nitems, nblocks, max_tile, dblob, st);
+    if (precision == kC128)
+        return tables ? run_batch<double, true>(ditems, nitems, nblocks, max_tile, dblob, st)
+                      : run_batch<double, false>(ditems, nitems, nblocks, max_tile, dblob, st);
+    return tables ? run_batch<float, true>(ditems, nitems, nblocks, max_tile, dblob, st)
+                  : run_batch<float, false>(ditems, nitems, nblocks, max_tile, dblob, st);
 }
 
 hipError_t launch_fused(const FusedLaunch& f, int precision, void* psi, const void* dblob, hipStream_t st) {
