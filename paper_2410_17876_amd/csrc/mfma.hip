@@ -19,14 +19,14 @@
 // classes are read completely before any of them is written, and tiles are
 // disjoint, so the update is in place.
 //
-// Gather and scatter walk a tile's elements in address order: when the lowest
-// qudits q0..q_{j-1} are all targets, their digits (the `inner` lowest address
-// digits, inner = their dims' product) vary fastest across lanes, then the
-// class, then the other targets' digits; rmap turns that order back into the
-// local index. Otherwise (inner = 1) lanes run over classes, whose lowest free
-// digit is q0. Either way a wavefront touches contiguous amplitudes (walking
-// the classes first with q0 a target would stride the lanes by d0 amplitudes
-// and cost up to 10x on the low-target gates).
+// Gather and scatter walk a tile's elements in address order: first the free
+// qudits below the lowest target (a run of F amplitudes; F = 1 when q0 is a
+// target), then the targets directly above them (the next `inner` address
+// digits), then the rest of the class id, then the other targets' digits; rmap
+// turns that order back into the local index. A tile then holds nt = F x
+// floor(NT / F) classes so that its columns are whole runs. A wavefront touches
+// contiguous amplitudes (walking the classes first would stride the lanes by
+// the targets' extent when a target is low, and cost up to 10x on such gates).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -50,13 +50,20 @@ struct MfmaShape {
     static constexpr int LOG_NT = NT == 128 ? 7 : (NT == 64 ? 6 : 5);
 };
 
+// Element order of a tile (see the header): F, inner and the classes per tile
+// nt (a multiple of F, at most NT), with their divisors; B = nt / F.
+struct MfmaOrder {
+    int F, inner, nt, B;
+    FastDiv<uint32_t> fdiv, idiv, bdiv;
+};
+
 template <int MP, typename I>
 __global__ __launch_bounds__(kMfmaBlock) void block_mfma_c64(typename Cx<float>::T* __restrict__ psi,
                                                              const Decode<I> dec, const int M, const I ntiles,
                                                              const float* __restrict__ A,
                                                              const I* __restrict__ off,
-                                                             const int32_t* __restrict__ rmap_g, const int inner,
-                                                             const FastDiv<uint32_t> idiv) {
+                                                             const int32_t* __restrict__ rmap_g,
+                                                             const MfmaOrder ord) {
     using T = typename Cx<float>::T;
     using S = MfmaShape<MP>;
     constexpr int K2 = 2 * MP;
@@ -91,27 +98,33 @@ __global__ __launch_bounds__(kMfmaBlock) void block_mfma_c64(typename Cx<float>:
     // the last MFMA of every tile then waits for the next tile's gather.
     __builtin_amdgcn_s_waitcnt(0);
 
+    const int nt = ord.nt;
     auto ncols_of = [&](I t) -> int {
-        const I left = dec.n_classes - t * (I)S::NT;
-        return left < (I)S::NT ? (int)left : S::NT;
+        const I left = dec.n_classes - t * (I)nt;
+        return left < (I)nt ? (int)left : nt;
     };
-    // Element e of a tile in address order: low = e mod inner (the low target
-    // digits), then the class c, then hi (the other target digits); r is the
-    // local index. Elements e >= M * NT do not exist; c >= ncols is past the
-    // last class. Such elements load element (0, 0) (in bounds, no branch, so
-    // the loads issue back to back) and are neither staged nor stored.
-    const int MN = M * S::NT;
+    // Element e of a tile in address order: f = e mod F (free low digits), then
+    // low (the inner target digits), then cb (the rest of the class id: class
+    // c = f + F cb), then hi (the other target digits); r is the local index.
+    // Elements e >= M * nt do not exist; c >= ncols is past the last class. Such
+    // elements load element (0, 0) (in bounds, no branch, so the loads issue back
+    // to back) and are neither staged nor stored.
+    const int MN = M * nt;
     auto element = [&](int e, int ncols, int* r, int* c) -> bool {
-        if (inner == 1) {  // uniform: lanes over classes, then members
+        if (ord.F == 1 && ord.inner == 1) {  // uniform: lanes over classes, then members
             *c = e & (S::NT - 1);
             *r = e >> S::LOG_NT;
             return e < MN && *c < ncols;
         }
-        const uint32_t q = fast_div<uint32_t>((uint32_t)e, idiv);
-        const int low = e - (int)q * inner;
+        const uint32_t q1 = fast_div<uint32_t>((uint32_t)e, ord.fdiv);
+        const int f = e - (int)q1 * ord.F;
+        const uint32_t q2 = fast_div<uint32_t>(q1, ord.idiv);
+        const int low = (int)(q1 - q2 * (uint32_t)ord.inner);
+        const uint32_t hi = fast_div<uint32_t>(q2, ord.bdiv);
+        const int cb = (int)(q2 - hi * (uint32_t)ord.B);
         const bool real = e < MN;
-        *c = (int)(q & (S::NT - 1));
-        *r = rmap[real ? low + inner * (int)(q >> S::LOG_NT) : 0];  // index < M for real elements
+        *c = f + ord.F * cb;
+        *r = rmap[real ? low + ord.inner * (int)hi : 0];  // index < M for real elements
         return real && *c < ncols;
     };
     auto gather = [&](T (&v)[EPT], int buf, int ncols) {
@@ -140,7 +153,7 @@ __global__ __launch_bounds__(kMfmaBlock) void block_mfma_c64(typename Cx<float>:
     int cur = 0;
     if (t < ntiles) {
         const int nc = ncols_of(t);
-        if ((int)threadIdx.x < nc) bases[0][threadIdx.x] = decode_base_rolled<I>(dec, t * (I)S::NT + (I)threadIdx.x);
+        if ((int)threadIdx.x < nc) bases[0][threadIdx.x] = decode_base_rolled<I>(dec, t * (I)nt + (I)threadIdx.x);
         __syncthreads();
         T v[EPT];
         gather(v, 0, nc);
@@ -152,7 +165,7 @@ __global__ __launch_bounds__(kMfmaBlock) void block_mfma_c64(typename Cx<float>:
         const bool has_next = tn < ntiles;
         const int ncols_next = has_next ? ncols_of(tn) : 0;
         if ((int)threadIdx.x < ncols_next)
-            bases[cur ^ 1][threadIdx.x] = decode_base_rolled<I>(dec, tn * (I)S::NT + (I)threadIdx.x);
+            bases[cur ^ 1][threadIdx.x] = decode_base_rolled<I>(dec, tn * (I)nt + (I)threadIdx.x);
         __syncthreads();  // tile t staged in Bs; next bases visible
         // Prefetch the next tile into registers; the loads land during this tile's work.
         T pv[EPT];
@@ -193,29 +206,47 @@ size_t mfma_gate_bytes(int M, bool narrow) {
     return K2 * K2 * sizeof(float) + (size_t)M * (narrow ? 4 : 8) + (size_t)M * 4;
 }
 
-// The address-order map of the gather (see the header): inner = the largest m
-// such that the member offsets include 0..m-1 (the lowest qudits are targets up
-// to that product), and rmap[low + inner * hi] = the local index whose offset is
-// low plus the hi-th smallest multiple of inner among the offsets.
-static int mfma_inner(const GatePlan& p) {
-    std::vector<bool> has(p.M + 1, false);
+// The gather's element order (see the header), from the gate's free segments
+// and member offsets: F = the lowest free run when it starts at q0 and a target
+// sits right above it (kept only while a tile still holds at least 7/8 of NT
+// classes), inner = the largest m with offsets 0, F, ..., (m-1) F all present,
+// and rmap[low + inner * hi] = the local index whose offset is low * F plus the
+// hi-th smallest of the remaining parts.
+struct Order {
+    int F, inner, nt;
+};
+
+static Order mfma_order(const GatePlan& p, int NT) {
+    int64_t step = 0;
     for (int a = 0; a < p.M; ++a)
-        if (p.off[a] >= 0 && p.off[a] <= p.M) has[(size_t)p.off[a]] = true;
-    int m = 0;
-    while (m < p.M && has[(size_t)m]) ++m;
-    return m < 1 ? 1 : m;
+        if (p.off[a] > 0 && (step == 0 || p.off[a] < step)) step = p.off[a];
+    int64_t F = 1;
+    if (p.nseg > 0 && p.seg_stride[0] == 1 && (int64_t)p.seg_size[0] == step) F = (int64_t)p.seg_size[0];
+    if (F > NT || F * (NT / F) * 8 < 7 * (int64_t)NT) F = 1;
+    std::vector<int64_t> offs(p.off, p.off + p.M);
+    std::sort(offs.begin(), offs.end());
+    int inner = 0;
+    while (inner < p.M && std::binary_search(offs.begin(), offs.end(), (int64_t)inner * F)) ++inner;
+    if (inner < 1) inner = 1;
+    return Order{(int)F, inner, (int)(F * (NT / F))};
 }
 
-static void mfma_rmap(const GatePlan& p, int inner, int32_t* rmap) {
+static void mfma_rmap(const GatePlan& p, const Order& o, int32_t* rmap) {
     std::vector<int64_t> his;
-    for (int a = 0; a < p.M; ++a) his.push_back(p.off[a] - p.off[a] % inner);
+    for (int a = 0; a < p.M; ++a) his.push_back(p.off[a] - ((p.off[a] / o.F) % o.inner) * o.F);
     std::sort(his.begin(), his.end());
     his.erase(std::unique(his.begin(), his.end()), his.end());
     for (int a = 0; a < p.M; ++a) {
-        const int64_t low = p.off[a] % inner;
-        const int64_t hi = std::lower_bound(his.begin(), his.end(), p.off[a] - low) - his.begin();
-        rmap[low + (int64_t)inner * hi] = a;
+        const int64_t low = (p.off[a] / o.F) % o.inner;
+        const int64_t hi =
+            std::lower_bound(his.begin(), his.end(), p.off[a] - low * o.F) - his.begin();
+        rmap[low + (int64_t)o.inner * hi] = a;
     }
+}
+
+static int mfma_nt(int M) {
+    const int MP = mfma_padded(M);
+    return MP == 32 ? MfmaShape<32>::NT : (MP == 64 ? MfmaShape<64>::NT : MfmaShape<128>::NT);
 }
 
 void fill_mfma_gate(const GatePlan& p, const double* U, void* dst) {
@@ -242,14 +273,23 @@ void fill_mfma_gate(const GatePlan& p, const double* U, void* dst) {
         for (int a = 0; a < p.M; ++a) oo[a] = (uint64_t)p.off[a];
     }
     int32_t* rm = reinterpret_cast<int32_t*>(o + (size_t)p.M * (narrow ? 4 : 8));
-    mfma_rmap(p, mfma_inner(p), rm);
+    mfma_rmap(p, mfma_order(p, mfma_nt(p.M)), rm);
 }
 
 template <int MP, typename I>
 static hipError_t run_mfma(const GatePlan& p, void* psi, const void* dgate, hipStream_t st) {
     using S = MfmaShape<MP>;
     const Decode<I> dec = make_decode<I>(p);
-    const uint64_t ntiles = (p.n_classes + S::NT - 1) / S::NT;
+    const Order o = mfma_order(p, S::NT);
+    MfmaOrder ord;
+    ord.F = o.F;
+    ord.inner = o.inner;
+    ord.nt = o.nt;
+    ord.B = o.nt / o.F;
+    ord.fdiv = make_fast_div<uint32_t>((uint64_t)o.F);
+    ord.idiv = make_fast_div<uint32_t>((uint64_t)o.inner);
+    ord.bdiv = make_fast_div<uint32_t>((uint64_t)ord.B);
+    const uint64_t ntiles = (p.n_classes + (uint64_t)o.nt - 1) / (uint64_t)o.nt;
     static int per_cu = 0;
     static int cus = 0;
     if (!per_cu) {
@@ -266,10 +306,8 @@ static hipError_t run_mfma(const GatePlan& p, void* psi, const void* dgate, hipS
     const I* off = reinterpret_cast<const I*>(static_cast<const unsigned char*>(dgate) +
                                               (size_t)(2 * MP) * (2 * MP) * sizeof(float));
     const int32_t* rmap = reinterpret_cast<const int32_t*>(off + p.M);
-    const int inner = mfma_inner(p);
     hipLaunchKernelGGL((block_mfma_c64<MP, I>), dim3((unsigned)grid), dim3(kMfmaBlock), 0, st,
-                       static_cast<typename Cx<float>::T*>(psi), dec, p.M, (I)ntiles, A, off, rmap, inner,
-                       make_fast_div<uint32_t>((uint64_t)inner));
+                       static_cast<typename Cx<float>::T*>(psi), dec, p.M, (I)ntiles, A, off, rmap, ord);
     return hipGetLastError();
 }
 

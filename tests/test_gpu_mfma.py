@@ -24,7 +24,7 @@ def round32(v):
     return v.real.astype(np.float32).astype(np.float64) + 1j * v.imag.astype(np.float32).astype(np.float64)
 
 
-CASES = [  # (dims, targets): M = 18, 25, 27, 36, 48, 49, 64, 100, 125, 126
+CASES = [  # (dims, targets): M = 18, 25, 27, 36, 48, 49, 64, 100, 125, 126, 25, 25, 25, 125
     ([2, 3, 3, 2, 5, 2, 3], [1, 2, 0]),
     ([5, 2, 5, 3, 2, 2, 3], [0, 2]),
     ([3, 3, 2, 3, 5, 2, 2], [0, 1, 3]),
@@ -35,6 +35,11 @@ CASES = [  # (dims, targets): M = 18, 25, 27, 36, 48, 49, 64, 100, 125, 126
     ([5, 3, 5, 4, 2, 3], [2, 3, 0]),
     ([5, 5, 5, 3, 2, 2, 2], [0, 1, 2]),
     ([2, 7, 6, 3, 3, 2], [1, 2, 3]),
+    # free qudits below the lowest target (gather order with a free low run F)
+    ([3, 5, 5, 2, 2, 3, 2], [1, 2]),       # F = 3
+    ([2, 2, 5, 5, 3, 2, 2], [3, 2]),       # F = 4
+    ([5, 5, 5, 5, 2, 3], [2, 3]),          # F = 25: 125 classes per tile
+    ([2, 5, 5, 5, 3, 2], [1, 2, 3]),       # F = 2, M = 125
 ]
 
 
@@ -138,3 +143,14 @@ def test_full_ququint_register_sampled():
     st.close()
     del st
     torch.cuda.empty_cache()
+
+
+def test_mfma_control_below_targets():
+    # a control on q0 under low targets: the plain class order (no free low run)
+    rng = np.random.default_rng(41)
+    dims = [3, 5, 5, 2, 2, 3, 2]
+    psi0 = rand_state(rng, math.prod(dims))
+    U = haar(25, rng)
+    st = qd().State(dims, "c64", init=None).set_amplitudes(psi0)
+    st.apply([1, 2], U, [0], [2])
+    assert_close(st.amplitudes(), oracle.apply(dims, round32(psi0), [1, 2], U, [0], [2]), "c64", "control on q0")
