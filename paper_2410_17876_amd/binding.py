@@ -139,6 +139,25 @@ class GateList:
     def __len__(self):
         return len(self.gates)
 
+    def view(self, start: int, count: int) -> "GateListView":
+        """Gates [start, start + count) without marshalling them again."""
+        start = max(0, min(start, len(self.gates)))
+        count = max(0, min(count, len(self.gates) - start))
+        return GateListView(self, start, count)
+
+
+class GateListView:
+    """A contiguous range of a GateList's records (shares its arrays)."""
+
+    def __init__(self, parent: GateList, start: int, count: int):
+        self.parent = parent
+        self.count = count
+        self.gates = parent.gates[start:start + count]
+        self.descs = C.cast(C.addressof(parent.descs) + start * C.sizeof(GateDesc), C.POINTER(GateDesc))
+
+    def __len__(self):
+        return self.count
+
 
 def _options(fuse=True, tile_amps=0, min_run=0) -> CircuitOptions:
     return CircuitOptions(1 if fuse else 0, int(tile_amps), int(min_run), 0, 0)
@@ -323,7 +342,7 @@ def _batch_args(states, gate_lists):
     n = len(states)
     if len(gate_lists) != n:
         raise ValueError("one gate list per state")
-    gls = [g if isinstance(g, GateList) else GateList(g) for g in gate_lists]
+    gls = [g if isinstance(g, (GateList, GateListView)) else GateList(g) for g in gate_lists]
     hs = (C.c_void_p * max(1, n))(*[st.handle for st in states])
     gp = (C.POINTER(GateDesc) * max(1, n))(*[C.cast(g.descs, C.POINTER(GateDesc)) for g in gls])
     counts = np.array([len(g) for g in gls] or [0], dtype=np.int32)

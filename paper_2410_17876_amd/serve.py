@@ -124,7 +124,7 @@ class Server:
             return False
         lists = []
         for r in work:
-            lists.append(GateList(r.gates.gates[r.pos:r.pos + self.quantum]))
+            lists.append(r.gates.view(r.pos, self.quantum))  # no re-marshalling per tick
             r.pos += len(lists[-1])
         self.batch.apply([r.state for r in work], lists, tile_amps=self.tile_amps, min_run=self.min_run)
         ev = self.torch.cuda.Event()
