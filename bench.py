@@ -217,14 +217,22 @@ def run_batched(qd, precision, steps, warmup, tune_cache):
     lists = [qd.GateList(s.gates()) for s in specs]
     log(f"batched {precision}: {len(specs)} circuits generated in {time.time() - t0:.1f} s "
         f"(sum D = {sum(s.D for s in specs)}, gates = {sum(len(g) for g in lists)})")
-    # Autotune the tile shape on a sample: 64 circuits, first 100 gates each.
+    # Autotune the tile shape on a sample: 64 circuits, first 100 gates each,
+    # timing graph replays of a compiled plan per candidate (what the timed run
+    # does); the tuner's untimed warm-up call of each candidate compiles it.
     sample = qd.batch.BatchRunner([s.dims for s in specs[:64]], precision)
     sample_lists = [qd.GateList(g.gates[:100]) for g in lists[:64]]
+    sample_plans = {}
 
     def trial(tile, run_len):
-        sample.run(sample_lists, tile_amps=tile, min_run=run_len)
+        if (tile, run_len) not in sample_plans:
+            sample_plans[(tile, run_len)] = sample.compile(sample_lists, tile_amps=tile, min_run=run_len)
+        sample_plans[(tile, run_len)].run(graph=True)
+        torch.cuda.synchronize()
 
-    tuned = qd.tune.tune(trial, precision, "batched-workload-v1", tune_cache)
+    tuned = qd.tune.tune(trial, precision, "batched-workload-v2", tune_cache)
+    for p in sample_plans.values():
+        p.close()
     sample.close()
     tile, run_len = tuned["tile_amps"], tuned["min_run"]
     log(f"batched {precision}: autotuned tile {tile}, min run {run_len} ({'cached' if tuned['cached'] else 'measured'})")

@@ -603,11 +603,8 @@ struct BatchInput {
     size_t rounds = 0;
 };
 
-// tables: ship each tile gate's class-base table (worth it for compiled plans,
-// uploaded once; eager rounds decode on the device to keep uploads small).
 int batch_validate_and_plan(int precision, qd_state* const* states, const qd_gate_desc* const* gates,
-                            const int32_t* counts, int32_t nstates, const qd_circuit_options* opts, bool tables,
-                            BatchInput& in) {
+                            const int32_t* counts, int32_t nstates, const qd_circuit_options* opts, BatchInput& in) {
     if (nstates < 0) return set_err(QD_ERR_INVALID_ARGUMENT, "negative state count");
     if (nstates > 0 && (!states || !gates || !counts))
         return set_err(QD_ERR_INVALID_ARGUMENT, "states, gates or counts is null");
@@ -630,7 +627,6 @@ int batch_validate_and_plan(int precision, qd_state* const* states, const qd_gat
     int rc = circuit_options(opts, precision, &co);
     if (rc) return rc;
     co.fuse = true;
-    co.tables = tables;
     co.single_as_fused = true;
     in.plans.assign(nstates, {});
     in.rounds = 0;
@@ -661,7 +657,7 @@ int build_round(qd_state* const* states, int32_t nstates, const BatchInput& in, 
         TileGate* tg = reinterpret_cast<TileGate*>(out.blob.data() + base + f.gates_off);
         for (int g = 0; g < f.ngates; ++g) {
             tg[g].u_off += (uint32_t)base;
-            if (tg[g].bases_off != kDecodeBases) tg[g].bases_off += (uint32_t)base;
+            tg[g].bases_off += (uint32_t)base;
         }
         BatchItem it;
         std::memset(&it, 0, sizeof it);
@@ -746,7 +742,7 @@ int qd_batch_apply(qd_batch* b, qd_state* const* states, const qd_gate_desc* con
     if (!b) return set_err(QD_ERR_INVALID_ARGUMENT, "batch is null");
     if (nstates == 0) return QD_OK;
     BatchInput in;
-    int rc = batch_validate_and_plan(b->precision, states, gates, counts, nstates, opts, false, in);
+    int rc = batch_validate_and_plan(b->precision, states, gates, counts, nstates, opts, in);
     if (rc) return rc;
     qd_state* s0 = states[0];
     rc = use_device(s0);
@@ -763,7 +759,7 @@ int qd_batch_apply(qd_batch* b, qd_state* const* states, const qd_gate_desc* con
             const unsigned char* dblob = nullptr;
             rc = batch_stage(b, hr.blob, st, &dblob);
             if (rc) return rc;
-            QD_HIP(launch_batch(b->precision, false, dblob + hr.items_off, hr.nitems, (uint32_t)hr.nblocks, hr.max_tile,
+            QD_HIP(launch_batch(b->precision, dblob + hr.items_off, hr.nitems, (uint32_t)hr.nblocks, hr.max_tile,
                                 dblob, st),
                    "batch launch");
             items_total += hr.nitems;
@@ -787,7 +783,7 @@ int qd_batch_compile(qd_state* const* states, const qd_gate_desc* const* gates, 
     if (nstates < 1 || !states || !states[0]) return set_err(QD_ERR_INVALID_ARGUMENT, "a plan needs at least one state");
     const int precision = states[0]->precision;
     BatchInput in;
-    int rc = batch_validate_and_plan(precision, states, gates, counts, nstates, opts, true, in);
+    int rc = batch_validate_and_plan(precision, states, gates, counts, nstates, opts, in);
     if (rc) return rc;
     qd_batch_plan* P = new qd_batch_plan();
     P->precision = precision;
@@ -842,7 +838,7 @@ namespace {
 hipError_t plan_enqueue(qd_batch_plan* P, hipStream_t st) {
     for (const auto& R : P->rounds) {
         if (!R.nitems) continue;
-        hipError_t e = launch_batch(P->precision, true, P->dev + R.blob_off + R.items_off, R.nitems, R.nblocks,
+        hipError_t e = launch_batch(P->precision, P->dev + R.blob_off + R.items_off, R.nitems, R.nblocks,
                                     R.max_tile,
                                     P->dev + R.blob_off, st);
         if (e != hipSuccess) return e;

@@ -23,16 +23,14 @@
 
 namespace qd {
 
-constexpr int kTileMaxSeg = 8;      // free segments of a tile-local plan
+constexpr int kTileMaxSeg = 8;      // free segments of a batched item's tile-index decoder
 constexpr int kFuseMaxM = 16;       // class size (dense) / active count (monomial) inside a tile
 constexpr int kFuseMaxGates = 64;   // gates per fused pass
 constexpr int kMaxOuterCtl = 8;     // controls outside S per gate
 
-// A gate's classes inside a tile are the same for every tile. A single-state
-// pass ships their tile-local bases as a uint16 table (a tile has at most 32768
-// amplitudes); a batched pass, whose descriptors are uploaded every round,
-// decodes them on the device instead (bases_off == kDecodeBases).
-constexpr uint32_t kDecodeBases = 0xffffffffu;
+// A gate's classes inside a tile are the same for every tile, so every pass
+// ships their tile-local bases as a uint16 table (a tile has at most 32768
+// amplitudes) instead of decoding them on the device.
 
 // Two consecutive dense gates on disjoint targets, both with classes of at most
 // kPairMaxM amplitudes and no controls, share one descriptor: a thread reads the
@@ -50,8 +48,7 @@ struct TileGate {
     int32_t M;           // dense: class size; pair: class size of the first gate; monomial: active entries
     int32_t M2;          // pair: class size of the second gate (its U follows the first's in the blob)
     uint32_t n_classes;                 // classes of the gate inside one tile
-    uint32_t bases_off;                 // byte offset of the uint16 class bases in the blob, or kDecodeBases
-    Decode<uint32_t, kTileMaxSeg> dec;  // tile-local class decoder
+    uint32_t bases_off;                 // byte offset of the uint16 class bases in the blob
     uint32_t off[kFuseMaxM];            // dense, pair: member offsets; monomial: source offsets
     uint32_t dst[kFuseMaxM];            // monomial: destination offsets
     uint32_t one_mask;                  // monomial: bit i set if factor i is exactly 1

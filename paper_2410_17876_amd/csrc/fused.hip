@@ -31,7 +31,7 @@ constexpr int class_unroll() {
 }
 
 // Class bases prefetched into registers: a thread's first kPre classes of a gate
-// (classes threadIdx.x + j * BS). With tables, a gate's bases are loaded while
+// (classes threadIdx.x + j * BS). A gate's bases are loaded from its table while
 // the previous gate (or the tile load) is still in flight, so the per-gate
 // chain does not wait for them; the first 2 * UF classes of a thread come from
 // here, the rest (only for gates with more classes per thread) are loaded in
@@ -39,22 +39,15 @@ constexpr int class_unroll() {
 constexpr int kPre = 8;
 
 template <int BS>
-__device__ __forceinline__ void prefetch_bases(const TileGate* __restrict__ G, const unsigned char* tables,
+__device__ __forceinline__ void prefetch_bases(const TileGate* __restrict__ G, const unsigned char* blob,
                                                uint32_t (&pre)[kPre]) {
-    const uint16_t* bases = reinterpret_cast<const uint16_t*>(tables + G->bases_off);
+    const uint16_t* bases = reinterpret_cast<const uint16_t*>(blob + G->bases_off);
     const uint32_t nc = G->n_classes;
 #pragma unroll
     for (int j = 0; j < kPre; ++j) {
         const uint32_t c = threadIdx.x + j * BS;
         pre[j] = bases[c < nc ? c : 0u];  // clamped: every load in bounds, none predicated
     }
-}
-
-// Class base c of gate G inside the tile: from its table, or decoded.
-template <bool TABLE>
-__device__ __forceinline__ uint32_t class_base(const TileGate* __restrict__ G, const uint16_t* bases, uint32_t c) {
-    if constexpr (TABLE) return (uint32_t)bases[c];
-    else return decode_base<uint32_t>(G->dec, c);
 }
 
 // Dense update of UF classes (the same arithmetic as the one-gate sweep).
@@ -132,14 +125,14 @@ __device__ __forceinline__ void mono_classes(typename Cx<R>::T* tile, const type
     }
 }
 
-// A gate's classes, in trips of UF per thread. With TABLE the first 2 * UF
-// classes of the thread take their bases from pre (static indices, so pre stays
-// in registers), the rest from the table; without, every base is decoded.
-template <int UF, int BS, bool TABLE, typename Body>
+// A gate's classes, in trips of UF per thread. The first 2 * UF classes of the
+// thread take their bases from pre (static indices, so pre stays in registers),
+// the rest from the table.
+template <int UF, int BS, typename Body>
 __device__ __forceinline__ void for_classes(const TileGate* __restrict__ G, const uint16_t* bases,
                                             const uint32_t (&pre)[kPre], const Body& body) {
     const uint32_t nc = G->n_classes;
-    constexpr int P1 = TABLE ? 2 * UF : 0;
+    constexpr int P1 = 2 * UF;
     static_assert(P1 <= kPre, "prefetched classes exceed kPre");
 #pragma unroll
     for (int t = 0; t < P1 / UF; ++t) {
@@ -159,13 +152,13 @@ __device__ __forceinline__ void for_classes(const TileGate* __restrict__ G, cons
 #pragma unroll
         for (int u = 0; u < UF; ++u) {
             ok[u] = c0 + u * BS < nc;
-            base[u] = class_base<TABLE>(G, bases, ok[u] ? c0 + u * BS : 0u);  // unconditional: no wait per load
+            base[u] = bases[ok[u] ? c0 + u * BS : 0u];  // unconditional: no wait per load
         }
         body(base, ok);
     }
 }
 
-template <typename R, int M, int BS, bool TABLE>
+template <typename R, int M, int BS>
 __device__ __forceinline__ void tile_dense(typename Cx<R>::T* tile, const TileGate* __restrict__ G,
                                            const typename Cx<R>::T* __restrict__ U, const uint16_t* bases,
                                            const uint32_t (&pre)[kPre]) {
@@ -173,12 +166,12 @@ __device__ __forceinline__ void tile_dense(typename Cx<R>::T* tile, const TileGa
     uint32_t off[M];
 #pragma unroll
     for (int a = 0; a < M; ++a) off[a] = G->off[a];
-    for_classes<UF, BS, TABLE>(G, bases, pre, [&](const uint32_t (&base)[UF], const bool (&ok)[UF]) {
+    for_classes<UF, BS>(G, bases, pre, [&](const uint32_t (&base)[UF], const bool (&ok)[UF]) {
         dense_classes<R, M, UF>(tile, G, U, off, base, ok);
     });
 }
 
-template <typename R, int A, int BS, bool TABLE>
+template <typename R, int A, int BS>
 __device__ __forceinline__ void tile_mono(typename Cx<R>::T* tile, const TileGate* __restrict__ G,
                                           const typename Cx<R>::T* __restrict__ lam, const uint16_t* bases,
                                           const uint32_t (&pre)[kPre]) {
@@ -190,7 +183,7 @@ __device__ __forceinline__ void tile_mono(typename Cx<R>::T* tile, const TileGat
         dst[i] = G->dst[i];
     }
     const uint32_t mask = G->one_mask;
-    for_classes<UF, BS, TABLE>(G, bases, pre, [&](const uint32_t (&base)[UF], const bool (&ok)[UF]) {
+    for_classes<UF, BS>(G, bases, pre, [&](const uint32_t (&base)[UF], const bool (&ok)[UF]) {
         mono_classes<R, A, UF>(tile, lam, src, dst, mask, base, ok);
     });
 }
@@ -250,7 +243,7 @@ __device__ __forceinline__ void pair_classes(typename Cx<R>::T* tile, const Tile
     }
 }
 
-template <typename R, int M1, int M2, int BS, bool TABLE>
+template <typename R, int M1, int M2, int BS>
 __device__ __forceinline__ void tile_pair(typename Cx<R>::T* tile, const TileGate* __restrict__ G,
                                           const typename Cx<R>::T* __restrict__ U, const uint16_t* bases,
                                           const uint32_t (&pre)[kPre]) {
@@ -260,7 +253,7 @@ __device__ __forceinline__ void tile_pair(typename Cx<R>::T* tile, const TileGat
 #pragma unroll
     for (int a = 0; a < J; ++a) off[a] = G->off[a];
     const typename Cx<R>::T* __restrict__ U2 = U + M1 * M1;  // the second gate's matrix follows the first's
-    for_classes<UF, BS, TABLE>(G, bases, pre, [&](const uint32_t (&base)[UF], const bool (&ok)[UF]) {
+    for_classes<UF, BS>(G, bases, pre, [&](const uint32_t (&base)[UF], const bool (&ok)[UF]) {
         pair_classes<R, M1, M2, UF>(tile, G, U, U2, off, base, ok);
     });
 }
@@ -274,25 +267,24 @@ __device__ __forceinline__ int next_live_gate(const TileGate* __restrict__ gates
     return g;
 }
 
-// The pass's gates applied to an LDS-resident tile. With TABLE every gate's
-// class bases come from its uint16 table at tables + bases_off, and pre holds
-// the prefetched bases of gate `first` (the first live gate, which the caller
-// prefetched); otherwise bases are decoded on the device and pre is unused.
-template <typename R, typename I, int BS, bool TABLE>
+// The pass's gates applied to an LDS-resident tile. Every gate's class bases
+// come from its uint16 table at blob + bases_off, and pre holds the prefetched
+// bases of gate `first` (the first live gate, which the caller prefetched).
+template <typename R, typename I, int BS>
 __device__ __forceinline__ void apply_gates(typename Cx<R>::T* tile, I obase, int ngates,
                                             const TileGate* __restrict__ gates,
-                                            const unsigned char* __restrict__ blob, const unsigned char* tables,
-                                            int first, uint32_t (&pre)[kPre]) {
+                                            const unsigned char* __restrict__ blob, int first,
+                                            uint32_t (&pre)[kPre]) {
     using T = typename Cx<R>::T;
     for (int g = first; g < ngates;) {
         // g is uniform; say so, so that descriptor reads become scalar loads
         const TileGate* __restrict__ G = gates + __builtin_amdgcn_readfirstlane(g);
         const T* U = reinterpret_cast<const T*>(blob + G->u_off);
-        const uint16_t* bases = TABLE ? reinterpret_cast<const uint16_t*>(tables + G->bases_off) : nullptr;
+        const uint16_t* bases = reinterpret_cast<const uint16_t*>(blob + G->bases_off);
         if (G->kind == kDensePair) {
             switch (G->M * 8 + G->M2) {
 #define QD_PAIR_CASE(m1, m2) \
-    case m1 * 8 + m2: tile_pair<R, m1, m2, BS, TABLE>(tile, G, U, bases, pre); break;
+    case m1 * 8 + m2: tile_pair<R, m1, m2, BS>(tile, G, U, bases, pre); break;
                 QD_PAIR_CASE(2, 2) QD_PAIR_CASE(2, 3) QD_PAIR_CASE(2, 4) QD_PAIR_CASE(3, 2) QD_PAIR_CASE(3, 3)
                 QD_PAIR_CASE(3, 4) QD_PAIR_CASE(4, 2) QD_PAIR_CASE(4, 3) QD_PAIR_CASE(4, 4)
 #undef QD_PAIR_CASE
@@ -301,7 +293,7 @@ __device__ __forceinline__ void apply_gates(typename Cx<R>::T* tile, I obase, in
         } else if (G->kind == kDense) {
             switch (G->M) {
 #define QD_DENSE_CASE(m) \
-    case m: tile_dense<R, m, BS, TABLE>(tile, G, U, bases, pre); break;
+    case m: tile_dense<R, m, BS>(tile, G, U, bases, pre); break;
                 QD_DENSE_CASE(2) QD_DENSE_CASE(3) QD_DENSE_CASE(4) QD_DENSE_CASE(5) QD_DENSE_CASE(6)
                 QD_DENSE_CASE(7) QD_DENSE_CASE(8) QD_DENSE_CASE(9) QD_DENSE_CASE(10) QD_DENSE_CASE(11)
                 QD_DENSE_CASE(12) QD_DENSE_CASE(13) QD_DENSE_CASE(14) QD_DENSE_CASE(15) QD_DENSE_CASE(16)
@@ -311,7 +303,7 @@ __device__ __forceinline__ void apply_gates(typename Cx<R>::T* tile, I obase, in
         } else {
             switch (G->M) {
 #define QD_MONO_CASE(m) \
-    case m: tile_mono<R, m, BS, TABLE>(tile, G, U, bases, pre); break;
+    case m: tile_mono<R, m, BS>(tile, G, U, bases, pre); break;
                 QD_MONO_CASE(1) QD_MONO_CASE(2) QD_MONO_CASE(3) QD_MONO_CASE(4) QD_MONO_CASE(5) QD_MONO_CASE(6)
                 QD_MONO_CASE(7) QD_MONO_CASE(8) QD_MONO_CASE(9) QD_MONO_CASE(10) QD_MONO_CASE(11)
                 QD_MONO_CASE(12) QD_MONO_CASE(13) QD_MONO_CASE(14) QD_MONO_CASE(15) QD_MONO_CASE(16)
@@ -322,7 +314,7 @@ __device__ __forceinline__ void apply_gates(typename Cx<R>::T* tile, I obase, in
         g = next_live_gate(gates, g + 1, ngates, (uint64_t)obase);
         // The next gate's bases are loaded before the barrier: they depend on no
         // tile data, and land while the slowest wavefront finishes this gate.
-        if (TABLE && g < ngates) prefetch_bases<BS>(gates + __builtin_amdgcn_readfirstlane(g), tables, pre);
+        if (g < ngates) prefetch_bases<BS>(gates + __builtin_amdgcn_readfirstlane(g), blob, pre);
         __syncthreads();
     }
 }
@@ -391,7 +383,7 @@ constexpr int fuse_block() {
     return sizeof(R) == 4 ? 512 : 256;
 }
 
-template <typename R, typename I, bool TABLE, int BS>
+template <typename R, typename I, int BS>
 __global__ __launch_bounds__(BS) void fused_tile(typename Cx<R>::T* __restrict__ psi, const FusedArgs<I> a,
                                                          const TileGate* __restrict__ gates,
                                                          const unsigned char* __restrict__ blob,
@@ -404,16 +396,16 @@ __global__ __launch_bounds__(BS) void fused_tile(typename Cx<R>::T* __restrict__
     const int first = next_live_gate(gates, 0, a.ngates, (uint64_t)obase);
     uint32_t pre[kPre];
     // The first gate's bases go out together with the tile's loads.
-    if (TABLE && first < a.ngates) prefetch_bases<BS>(gates + __builtin_amdgcn_readfirstlane(first), blob, pre);
+    if (first < a.ngates) prefetch_bases<BS>(gates + __builtin_amdgcn_readfirstlane(first), blob, pre);
     move_tile<T, I, true, BS>(psi, tile, obase, geo, run_off);
     __syncthreads();
-    apply_gates<R, I, BS, TABLE>(tile, obase, a.ngates, gates, blob, blob, first, pre);
+    apply_gates<R, I, BS>(tile, obase, a.ngates, gates, blob, first, pre);
     move_tile<T, I, false, BS>(psi, tile, obase, geo, run_off);
 }
 
 // A batched round: workgroup b processes tile (b - first_block) of the item
 // whose block range holds b (binary search over the items' first blocks).
-template <typename R, int BS, bool TABLE>
+template <typename R, int BS>
 __global__ __launch_bounds__(BS) void batch_tile(const BatchItem* __restrict__ items, int nitems,
                                                          const unsigned char* __restrict__ blob) {
     using T = typename Cx<R>::T;
@@ -434,10 +426,10 @@ __global__ __launch_bounds__(BS) void batch_tile(const BatchItem* __restrict__ i
     const TileGate* __restrict__ gates = reinterpret_cast<const TileGate*>(blob + it->gates_off);
     const int first = next_live_gate(gates, 0, it->ngates, (uint64_t)obase);
     uint32_t pre[kPre];
-    if (TABLE && first < it->ngates) prefetch_bases<BS>(gates + __builtin_amdgcn_readfirstlane(first), blob, pre);
+    if (first < it->ngates) prefetch_bases<BS>(gates + __builtin_amdgcn_readfirstlane(first), blob, pre);
     move_tile<T, uint32_t, true, BS>(psi, tile, obase, geo, run_off);
     __syncthreads();
-    apply_gates<R, uint32_t, BS, TABLE>(tile, obase, it->ngates, gates, blob, blob, first, pre);
+    apply_gates<R, uint32_t, BS>(tile, obase, it->ngates, gates, blob, first, pre);
     move_tile<T, uint32_t, false, BS>(psi, tile, obase, geo, run_off);
 }
 
@@ -479,32 +471,28 @@ static hipError_t run_fused(const FusedLaunch& f, void* psi, const void* dblob, 
     const I* ro = reinterpret_cast<const I*>(b + f.run_off_off);
     const size_t tile_bytes = (size_t)f.tile * sizeof(T);
     constexpr int BS = fuse_block<R>();
-    if (f.tables) return launch_tile<fused_tile<R, I, true, BS>>(f, BS, tile_bytes, st, static_cast<T*>(psi), a, tg, b, ro);
-    return launch_tile<fused_tile<R, I, false, BS>>(f, BS, tile_bytes, st, static_cast<T*>(psi), a, tg, b, ro);
+    return launch_tile<fused_tile<R, I, BS>>(f, BS, tile_bytes, st, static_cast<T*>(psi), a, tg, b, ro);
 }
 
-template <typename R, bool TABLE>
+template <typename R>
 static hipError_t run_batch(const void* ditems, int nitems, uint32_t nblocks, uint32_t max_tile, const void* dblob,
                             hipStream_t st) {
     using T = typename Cx<R>::T;
     const size_t shmem = (size_t)max_tile * sizeof(T);
     constexpr int BS = fuse_block<R>();
-    hipError_t e = allow_lds(batch_tile<R, BS, TABLE>, shmem);
+    hipError_t e = allow_lds(batch_tile<R, BS>, shmem);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((batch_tile<R, BS, TABLE>), dim3(nblocks), dim3(BS), shmem, st,
+    hipLaunchKernelGGL((batch_tile<R, BS>), dim3(nblocks), dim3(BS), shmem, st,
                        static_cast<const BatchItem*>(ditems), nitems, static_cast<const unsigned char*>(dblob));
     return hipGetLastError();
 }
 
-hipError_t launch_batch(int precision, bool tables, const void* ditems, int nitems, uint32_t nblocks,
-                        uint32_t max_tile, const void* dblob, hipStream_t st) {
+hipError_t launch_batch(int precision, const void* ditems, int nitems, uint32_t nblocks, uint32_t max_tile,
+                        const void* dblob, hipStream_t st) {
     if (nitems <= 0 || nblocks == 0) return hipSuccess;
     if (nblocks > 0x7fffffffu) return hipErrorInvalidValue;
-    if (precision == kC128)
-        return tables ? run_batch<double, true>(ditems, nitems, nblocks, max_tile, dblob, st)
-                      : run_batch<double, false>(ditems, nitems, nblocks, max_tile, dblob, st);
-    return tables ? run_batch<float, true>(ditems, nitems, nblocks, max_tile, dblob, st)
-                  : run_batch<float, false>(ditems, nitems, nblocks, max_tile, dblob, st);
+    return precision == kC128 ? run_batch<double>(ditems, nitems, nblocks, max_tile, dblob, st)
+                              : run_batch<float>(ditems, nitems, nblocks, max_tile, dblob, st);
 }
 
 hipError_t launch_fused(const FusedLaunch& f, int precision, void* psi, const void* dblob, hipStream_t st) {

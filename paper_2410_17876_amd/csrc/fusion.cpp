@@ -34,7 +34,7 @@ void put_complex(unsigned char* dst, double re, double im) {
 }  // namespace
 
 int build_fused(const int32_t* dims, int n, int precision, const CircuitGate* gates, const std::vector<int>& idx,
-                const std::vector<int>& S, int p_low, bool tables, PassPlan* out, std::string* err) {
+                const std::vector<int>& S, int p_low, PassPlan* out, std::string* err) {
     uint64_t s[QD_MAX_QUDITS];
     s[0] = 1;
     for (int i = 1; i < n; ++i) s[i] = s[i - 1] * (uint64_t)dims[i - 1];
@@ -113,10 +113,6 @@ int build_fused(const int32_t* dims, int n, int precision, const CircuitGate* ga
         int rc = plan_gate(tdims, nS, L.lt, g.k, lc, lv, mi, g.U, &L.plan, err);
         if (rc) return rc;
         if (L.plan.category == kIdentity) continue;
-        if (L.plan.nseg > kTileMaxSeg) {
-            *err = "tile-local plan has too many segments";
-            return QD_ERR_NOT_SUPPORTED;
-        }
         locs.push_back(std::move(L));
     }
     auto pairable = [&](const Local& A, const Local& B) {
@@ -137,17 +133,13 @@ int build_fused(const int32_t* dims, int n, int precision, const CircuitGate* ga
             else put_complex<float>(dst + i * ab, U[2 * i], U[2 * i + 1]);
         }
     };
-    auto put_classes = [&](TileGate& t, const GatePlan& gp) {
+    auto put_classes = [&](TileGate& t, const GatePlan& gp) {  // tile-local class bases, decoded once here
         t.n_classes = (uint32_t)gp.n_classes;
-        t.dec = make_decode<uint32_t, kTileMaxSeg>(gp);
-        t.bases_off = kDecodeBases;
-        if (tables) {  // tile-local class bases, decoded once here for every tile
-            t.bases_off = (uint32_t)udata.size();
-            const Decode<uint64_t> dec = make_decode<uint64_t>(gp);
-            udata.resize(align_up(udata.size() + 2 * (size_t)gp.n_classes, 16));
-            uint16_t* b = reinterpret_cast<uint16_t*>(udata.data() + t.bases_off);
-            for (uint64_t c = 0; c < gp.n_classes; ++c) b[c] = (uint16_t)decode_base<uint64_t>(dec, c);
-        }
+        t.bases_off = (uint32_t)udata.size();
+        const Decode<uint64_t> dec = make_decode<uint64_t>(gp);
+        udata.resize(align_up(udata.size() + 2 * (size_t)gp.n_classes, 16));
+        uint16_t* b = reinterpret_cast<uint16_t*>(udata.data() + t.bases_off);
+        for (uint64_t c = 0; c < gp.n_classes; ++c) b[c] = (uint16_t)decode_base_rolled<uint64_t>(dec, c);
     };
     GatePlan joint;  // geometry of a pair's joint class
     for (size_t i = 0; i < locs.size(); ++i) {
@@ -166,10 +158,6 @@ int build_fused(const int32_t* dims, int n, int precision, const CircuitGate* ga
             GatePlan& jp = joint;
             int rc = plan_gate(tdims, nS, jt, A.k + B.k, nullptr, nullptr, 0, eye.data(), &jp, err);
             if (rc) return rc;
-            if (jp.nseg > kTileMaxSeg) {
-                *err = "tile-local plan has too many segments";
-                return QD_ERR_NOT_SUPPORTED;
-            }
             put_classes(t, jp);
             t.kind = kDensePair;
             t.M = A.plan.M;
@@ -206,7 +194,6 @@ int build_fused(const int32_t* dims, int n, int precision, const CircuitGate* ga
         tg.push_back(t);
     }
     f.ngates = (int)tg.size();
-    f.tables = tables;
 
     // Blob: [TileGate x ngates][gate data][run offsets]. Descriptors' u_off are
     // relative to the start of the gate data; rebase them to the blob start.
@@ -214,7 +201,7 @@ int build_fused(const int32_t* dims, int n, int precision, const CircuitGate* ga
     const size_t data_off = align_up(sizeof(TileGate) * tg.size(), 16);
     for (TileGate& t : tg) {
         t.u_off += (uint32_t)data_off;
-        if (t.bases_off != kDecodeBases) t.bases_off += (uint32_t)data_off;
+        t.bases_off += (uint32_t)data_off;
     }
     f.run_off_off = align_up(data_off + udata.size(), 16);
     const bool narrow = D < (1ull << 31);
@@ -293,7 +280,7 @@ int plan_circuit(const int32_t* dims, int n, int precision, const CircuitGate* g
             std::vector<int> S;
             for (int q = 0; q < n; ++q)
                 if (inS[q]) S.push_back(q);
-            int r2 = build_fused(dims, n, precision, gates, cur, S, p_low, opt.tables, &pp, err);
+            int r2 = build_fused(dims, n, precision, gates, cur, S, p_low, &pp, err);
             if (r2) return r2;
         }
         out.push_back(std::move(pp));

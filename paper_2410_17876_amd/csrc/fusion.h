@@ -25,7 +25,6 @@ struct CircuitOptions {
     bool fuse = true;
     uint64_t tile_max = 4096;       // amplitudes per tile
     uint64_t min_run = 64;          // minimum contiguous run inside a tile
-    bool tables = true;             // ship tile-local class bases (else decode on the device)
     bool single_as_fused = false;   // run a one-gate pass as a tile pass too (batched rounds)
 };
 

@@ -50,15 +50,13 @@ struct FusedLaunch {
     int ngates;
     size_t gates_off;
     size_t run_off_off;
-    bool tables;  // every gate ships its class-base table (else the kernel decodes class bases)
 };
 hipError_t launch_fused(const FusedLaunch& f, int precision, void* psi, const void* dblob, hipStream_t stream);
 
 // A batched round (fused.h BatchItem): ditems/dblob are device copies; nblocks =
-// total tiles over all items; max_tile = largest tile (LDS per workgroup);
-// tables: the round's tile gates carry class-base tables (else decoded).
-hipError_t launch_batch(int precision, bool tables, const void* ditems, int nitems, uint32_t nblocks,
-                        uint32_t max_tile, const void* dblob, hipStream_t stream);
+// total tiles over all items; max_tile = largest tile (LDS per workgroup).
+hipError_t launch_batch(int precision, const void* ditems, int nitems, uint32_t nblocks, uint32_t max_tile,
+                        const void* dblob, hipStream_t stream);
 
 // Reductions and fills (reduce.hip).
 constexpr int kRedBlocks = 1024;

@@ -59,12 +59,14 @@ def test_budget_is_respected_and_oversized_rejected():
 def test_arrivals_join_while_others_run():
     # a long request arrives first; short ones arrive while it runs and must be
     # admitted -- and finish -- before it does
-    specs, reqs = make_requests(12, qps=500.0, lo=1e3, hi=1e4, depth_lo=10, depth_hi=20, seed=33)
-    long_spec = circuits.CircuitSpec([2] * 26, 300, 77)
+    # (the long one: 2^27 amplitudes, 600 gates, 2 gates per tick -- about 300
+    # ticks, far longer than the ~15 ms over which the short ones arrive)
+    specs, reqs = make_requests(12, qps=1000.0, lo=1e3, hi=1e4, depth_lo=10, depth_hi=20, seed=33)
+    long_spec = circuits.CircuitSpec([2] * 27, 600, 77)
     long_req = qd().serve.ServeRequest(100, 0.0, long_spec.dims, qd().GateList(long_spec.gates()))
     for r in reqs:
         r.arrival += 0.005
-    srv = qd().serve.Server("c64", quantum=4)
+    srv = qd().serve.Server("c64", quantum=2)
     srv.run([long_req] + reqs, realtime=True)
     shorts = [r for r in srv.finished if r.rid != 100]
     assert all(r.admitted < long_req.finished for r in shorts)
