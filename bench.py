@@ -277,47 +277,55 @@ def run_batched(qd, precision, steps, warmup, tune_cache):
                          "note": "whole-run average over all rounds: 2 x D x bytes per (state, pass)"}}
 
 
-def run_served(qd, n_closed, n_open, load):
+def run_served(qd, n_closed, n_open, loads):
     """The served workload: requests with log-uniform sizes in [1e3, 1e8]
     amplitudes (d in 2..7), depth 50..500 of the basic mix, complex64, admitted
     under a 200 GB HBM budget. First the closed-loop capacity (all requests
-    present at t = 0), then open-loop Poisson arrivals at `load` x capacity."""
+    present at t = 0), then open-loop Poisson arrivals at each of `loads` x
+    capacity. One request stream is generated (at rate 1/s) and reused: Poisson
+    arrivals at rate q are the rate-1 arrival times divided by q."""
     import torch
     from qd_inputs import circuits
 
-    def build(count, qps):
-        t0 = time.time()
-        specs = circuits.served_requests(qps=qps, count=count)
-        reqs = qd.serve.requests_from_specs(specs)
-        log(f"served: {count} requests generated in {time.time() - t0:.1f} s "
-            f"(sum D = {sum(r.D for r in reqs):.3g}, gates = {sum(len(r.gates) for r in reqs)})")
-        return reqs
+    t0 = time.time()
+    n = max(n_closed, n_open)
+    specs = circuits.served_requests(qps=1.0, count=n)
+    base = qd.serve.requests_from_specs(specs)
+    log(f"served: {n} requests generated in {time.time() - t0:.1f} s "
+        f"(sum D = {sum(r.D for r in base):.3g}, gates = {sum(len(r.gates) for r in base)})")
+
+    def fresh(count, rate):
+        return [qd.serve.ServeRequest(r.rid, r.arrival / rate if rate else 0.0, r.dims, r.gates) for r in base[:count]]
 
     upd = lambda reqs: sum(qd.gate_info(r.dims, g.targets, g.U, g.controls, g.values, "c64")["updated"]
                            for r in reqs for g in r.gates.gates)
-    warm = build(16, 1.0)
     srv = qd.serve.Server("c64", budget_bytes=200e9, quantum=32)
-    srv.run(warm, realtime=False)
+    srv.run(fresh(16, 0), realtime=False)  # warm-up
     srv.close()
-    closed = build(n_closed, 1.0)
+    closed = fresh(n_closed, 0)
     srv = qd.serve.Server("c64", budget_bytes=200e9, quantum=32)
     rc = srv.run(closed, realtime=False)
     srv.close()
     cap = rc["throughput_rps"]
     log(f"served: closed-loop capacity {cap:.1f} requests/s ({rc['wall_s']:.2f} s for {n_closed})")
-    opened = build(n_open, load * cap)
-    srv = qd.serve.Server("c64", budget_bytes=200e9, quantum=32)
-    ro = srv.run(opened, realtime=True)
-    srv.close()
+    opened = {}
+    for load in loads:
+        reqs = fresh(n_open, load * cap)
+        srv = qd.serve.Server("c64", budget_bytes=200e9, quantum=32)
+        ro = srv.run(reqs, realtime=True)
+        srv.close()
+        ro = dict(ro, offered_rps=load * cap, load=load, updates_per_s=upd(reqs) / ro["wall_s"])
+        opened[f"{load:.2f}"] = ro
+        log(f"served: open loop at {load:.2f} x capacity: p50 {ro['p50_ms']:.1f} ms, p99 {ro['p99_ms']:.1f} ms")
     torch.cuda.empty_cache()
-    log(f"served: open loop at {load:.2f} x capacity: p50 {ro['p50_ms']:.1f} ms, p99 {ro['p99_ms']:.1f} ms")
+    main = opened[f"{loads[len(loads) // 2]:.2f}"]
     return {"workload": "Poisson arrivals, sizes log-uniform 1e3..1e8 amplitudes (d in 2..7), depth 50..500, "
                         "basic gate mix, complex64, 200 GB HBM budget (seed 1003)",
-            "value": upd(opened) / ro["wall_s"], "unit": "updates/s", "dtype": "f32",
+            "value": main["updates_per_s"], "unit": "updates/s", "dtype": "f32",
             "closed_loop": {"requests": n_closed, "capacity_rps": cap, "wall_s": rc["wall_s"],
                             "updates_per_s": upd(closed) / rc["wall_s"], "p50_ms": rc["p50_ms"],
                             "p99_ms": rc["p99_ms"]},
-            "open_loop": dict(ro, offered_rps=load * cap, load=load),
+            "open_loop": opened,
             "latency": "arrival -> final state resident and its FP64 norm returned to the host"}
 
 
@@ -350,9 +358,11 @@ def main() -> int:
     ap.add_argument("--no-ququint", action="store_true", help="skip the 12-ququint MFMA workload")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-circuit batched workload")
     ap.add_argument("--no-served", action="store_true", help="skip the served (continuous batching) workload")
-    ap.add_argument("--served-closed", type=int, default=120, help="requests in the closed-loop capacity run")
-    ap.add_argument("--served-open", type=int, default=240, help="requests in the open-loop run")
-    ap.add_argument("--served-load", type=float, default=0.8, help="open-loop load as a fraction of capacity")
+    ap.add_argument("--served-closed", type=int, default=600,
+                    help="requests in the closed-loop capacity run (the same stream as the open-loop runs)")
+    ap.add_argument("--served-open", type=int, default=600, help="requests in each open-loop run")
+    ap.add_argument("--served-loads", default="0.5,0.8,0.95",
+                    help="open-loop loads as fractions of the closed-loop capacity")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "tune_cache.json"),
                     help="autotuner cache file")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -411,7 +421,8 @@ def main() -> int:
         for p in (["c64", "c128"] if not args.no_c64 else ["c128"]):
             res[f"batched_{p}"] = run_batched(qd, p, args.steps, args.warmup, args.tune_cache)
     if not args.no_served:
-        res["served"] = run_served(qd, args.served_closed, args.served_open, args.served_load)
+        res["served"] = run_served(qd, args.served_closed, args.served_open,
+                                   [float(x) for x in args.served_loads.split(",")])
     cpu = None
     if host is not None:
         cpu = cpu_baseline(qd, dims, gates, host, args.cpu_seconds)
