@@ -3,8 +3,9 @@
 Requests (a register's dims and a gate list) arrive over time. The server keeps
 admitted requests' statevectors resident on the GPU and advances all of them
 together: every scheduler tick takes the next quantum of gates of every
-resident request and applies them in one batched call (qd_batch_apply: one
-launch per round across all requests). A request that arrives while others
+resident request (more gates for smaller registers, so that each request's
+share of a tick is about the same device work) and applies them in one batched
+call (qd_batch_apply: one launch per round across all requests). A request that arrives while others
 are running is admitted at the next tick as soon as a slot and enough of the
 HBM budget are free; a finished request's memory is released at once. The host
 prepares tick k+1 while the device runs tick k; completion is observed through
@@ -53,7 +54,8 @@ class ServeRequest:
 
 class Server:
     def __init__(self, precision: str = "c64", budget_bytes: float = 200e9, max_slots: int = 256,
-                 quantum: int = 32, tile_amps: int = 0, min_run: int = 0, keep_states: bool = False):
+                 quantum: int = 32, tile_amps: int = 0, min_run: int = 0, keep_states: bool = False,
+                 tick_updates: float = 5e8):
         import torch
 
         self.torch = torch
@@ -61,7 +63,12 @@ class Server:
         self.amp_bytes = 16 if precision == "c128" else 8
         self.budget = float(budget_bytes)
         self.max_slots = max_slots
+        # Gates per request per tick: about tick_updates gate-amplitude updates
+        # (a millisecond or so of device work), at least `quantum`. Small
+        # requests then finish in one or a few ticks instead of len(gates) /
+        # quantum ticks, each as long as the largest resident request's quantum.
         self.quantum = quantum
+        self.tick_updates = tick_updates
         self.tile_amps, self.min_run = tile_amps, min_run
         self.keep_states = keep_states
         self.batch = Batch(precision)
@@ -124,7 +131,8 @@ class Server:
             return False
         lists = []
         for r in work:
-            lists.append(r.gates.view(r.pos, self.quantum))  # no re-marshalling per tick
+            q = max(self.quantum, int(self.tick_updates // r.D))
+            lists.append(r.gates.view(r.pos, q))  # no re-marshalling per tick
             r.pos += len(lists[-1])
         self.batch.apply([r.state for r in work], lists, tile_amps=self.tile_amps, min_run=self.min_run)
         ev = self.torch.cuda.Event()
