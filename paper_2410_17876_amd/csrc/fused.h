@@ -17,6 +17,7 @@
 // and becomes a per-tile predicate on the tile's base address.
 #pragma once
 
+#include <stddef.h>
 #include <stdint.h>
 
 #include "plan.h"
@@ -25,7 +26,7 @@ namespace qd {
 
 constexpr int kTileMaxSeg = 8;      // free segments of a batched item's tile-index decoder
 constexpr int kFuseMaxM = 16;       // class size (dense) / active count (monomial) inside a tile
-constexpr int kFuseMaxGates = 64;   // gates per fused pass
+constexpr size_t kPassBlobMax = 1536u << 10;  // device data of one fused pass (fits a 2 MB staging slot)
 constexpr int kMaxOuterCtl = 8;     // controls outside S per gate
 
 // A gate's classes inside a tile are the same for every tile, so every pass

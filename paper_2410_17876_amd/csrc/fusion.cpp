@@ -248,6 +248,12 @@ int plan_circuit(const int32_t* dims, int n, int precision, const CircuitGate* g
     std::vector<int> cur;
     bool inS[QD_MAX_QUDITS] = {false};
     uint64_t prodS = 0;
+    // Upper bound of the pass's device data (descriptor, class-base table of at
+    // most tile_max / 2 classes, matrix): a pass must fit one staging slot.
+    size_t blob_est = 0;
+    auto gate_bytes = [&](const GatePlan& p) {
+        return sizeof(TileGate) + tile_max + (size_t)p.M * p.M * 16 + 64;
+    };
 
     auto prod_with = [&](const CircuitGate& g) {
         uint64_t pr = prodS;
@@ -294,16 +300,18 @@ int plan_circuit(const int32_t* dims, int n, int precision, const CircuitGate* g
         if (rc) break;
         if (gp->category == kIdentity) continue;
         const bool can = opt.fuse && fusable(*gp, g.m);
-        if (can && !cur.empty() && prod_with(g) <= tile_max) {
+        if (can && !cur.empty() && prod_with(g) <= tile_max && blob_est + gate_bytes(*gp) <= kPassBlobMax) {
             for (int l = 0; l < g.k; ++l)
                 if (!inS[g.targets[l]]) {
                     inS[g.targets[l]] = true;
                     prodS *= (uint64_t)dims[g.targets[l]];
                 }
             cur.push_back(i);
+            blob_est += gate_bytes(*gp);
             continue;
         }
         if ((rc = close_pass())) break;
+        blob_est = 0;
         if (can) {
             open_pass();
             if (prod_with(g) <= tile_max) {
@@ -313,6 +321,7 @@ int plan_circuit(const int32_t* dims, int n, int precision, const CircuitGate* g
                         prodS *= (uint64_t)dims[g.targets[l]];
                     }
                 cur.push_back(i);
+                blob_est += gate_bytes(*gp);
                 continue;
             }
         }

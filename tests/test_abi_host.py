@@ -214,3 +214,18 @@ def test_one_hip_runtime_whatever_the_import_order():
                          capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip().splitlines()[-1] == "1"
+
+
+def test_circuit_plan_bounds_the_device_data_of_a_pass():
+    # with the largest tiles a pass's class-base tables grow with its gate
+    # count; passes are closed before their device data outgrows a staging slot
+    from qd_inputs import haar, Gate
+    rng = np.random.default_rng(8)
+    dims = [2] * 20
+    gates = [Gate((int(rng.integers(0, 15)),), haar(2, rng)) for _ in range(300)]
+    plan = qd.circuit_plan(dims, gates, "c64", tile_amps=16384, min_run=128)
+    assert sum(g for g, _ in plan) == len(gates)
+    assert max(g for g, _ in plan) <= 95           # about 1.5 MB / (16 KB of table + descriptor) per gate
+    assert len(plan) >= 4                          # the bound, not the targets, closed the passes
+    small = qd.circuit_plan(dims, gates, "c64", tile_amps=1024, min_run=64)
+    assert len(small) >= len(plan)                 # smaller tiles hold fewer targets per pass

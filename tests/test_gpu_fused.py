@@ -150,3 +150,19 @@ def test_dense_pairs_bitwise(precision):
     for g in gates:
         oracle.apply_gate(dims, ref, g)
     assert_close(fused.amplitudes(), ref, precision, "dense pairs")
+
+
+def test_long_passes_with_large_tiles():
+    # 300 gates on the low qubits with 16384-amplitude tiles: passes are cut by
+    # the bound on their device data, and the result is the sequential one
+    q = qd()
+    rng = np.random.default_rng(8)
+    dims = [2] * 20
+    gates = [Gate((int(rng.integers(0, 15)),), haar(2, rng)) for _ in range(300)]
+    psi0 = rand_state(rng, math.prod(dims))
+    a = q.State(dims, "c64", init=None).set_amplitudes(psi0)
+    info = a.run_circuit(gates, tile_amps=16384, min_run=128)
+    assert info["fused_passes"] >= 4
+    b = q.State(dims, "c64", init=None).set_amplitudes(psi0)
+    b.run(gates)
+    assert np.array_equal(a.amplitudes(), b.amplitudes())
