@@ -249,10 +249,11 @@ int plan_circuit(const int32_t* dims, int n, int precision, const CircuitGate* g
     bool inS[QD_MAX_QUDITS] = {false};
     uint64_t prodS = 0;
     // Upper bound of the pass's device data (descriptor, class-base table of at
-    // most tile_max / 2 classes, matrix): a pass must fit one staging slot.
+    // most tile / 2 classes, matrix): a pass must fit one staging slot.
+    const uint64_t tile_bound = std::min<uint64_t>(tile_max, D);
     size_t blob_est = 0;
     auto gate_bytes = [&](const GatePlan& p) {
-        return sizeof(TileGate) + tile_max + (size_t)p.M * p.M * 16 + 64;
+        return sizeof(TileGate) + (size_t)tile_bound + (size_t)p.M * p.M * 16 + 64;
     };
 
     auto prod_with = [&](const CircuitGate& g) {
