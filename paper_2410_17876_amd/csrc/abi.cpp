@@ -207,10 +207,10 @@ int qd_class_bases(const int32_t* dims, int32_t n, const int32_t* targets, int32
     const bool narrow = p->D < (1ull << 31);
     if (narrow) {
         const Decode<uint32_t> dec = make_decode<uint32_t>(*p);
-        for (uint64_t i = 0; i < count; ++i) bases[i] = decode_base_rolled<uint32_t>(dec, (uint32_t)(first + i));
+        for (uint64_t i = 0; i < count; ++i) bases[i] = decode_base<uint32_t>(dec, (uint32_t)(first + i));
     } else {
         const Decode<uint64_t> dec = make_decode<uint64_t>(*p);
-        for (uint64_t i = 0; i < count; ++i) bases[i] = decode_base_rolled<uint64_t>(dec, first + i);
+        for (uint64_t i = 0; i < count; ++i) bases[i] = decode_base<uint64_t>(dec, first + i);
     }
     delete p;
     return QD_OK;

@@ -391,7 +391,7 @@ __global__ __launch_bounds__(BS) void fused_tile(typename Cx<R>::T* __restrict__
     using T = typename Cx<R>::T;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* tile = reinterpret_cast<T*>(smem_raw);
-    const I obase = decode_base_rolled<I>(a.outer, (I)xcd_block());
+    const I obase = decode_base<I>(a.outer, (I)xcd_block());
     const TileGeom geo{a.tile, a.L, a.chunks_per_run, a.nchunks, a.cdiv};
     const int first = next_live_gate(gates, 0, a.ngates, (uint64_t)obase);
     uint32_t pre[kPre];
@@ -419,7 +419,7 @@ __global__ __launch_bounds__(BS) void batch_tile(const BatchItem* __restrict__ i
         else hi = mid - 1;
     }
     const BatchItem* __restrict__ it = items + __builtin_amdgcn_readfirstlane(lo);
-    const uint32_t obase = decode_base_rolled<uint32_t>(it->outer, b - it->first_block);
+    const uint32_t obase = decode_base<uint32_t>(it->outer, b - it->first_block);
     const TileGeom geo{it->tile, it->L, it->chunks_per_run, it->nchunks, it->cdiv};
     T* psi = reinterpret_cast<T*>(it->psi);
     const uint32_t* run_off = reinterpret_cast<const uint32_t*>(blob + it->run_off_off);

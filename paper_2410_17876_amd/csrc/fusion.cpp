@@ -139,7 +139,7 @@ int build_fused(const int32_t* dims, int n, int precision, const CircuitGate* ga
         const Decode<uint64_t> dec = make_decode<uint64_t>(gp);
         udata.resize(align_up(udata.size() + 2 * (size_t)gp.n_classes, 16));
         uint16_t* b = reinterpret_cast<uint16_t*>(udata.data() + t.bases_off);
-        for (uint64_t c = 0; c < gp.n_classes; ++c) b[c] = (uint16_t)decode_base_rolled<uint64_t>(dec, c);
+        for (uint64_t c = 0; c < gp.n_classes; ++c) b[c] = (uint16_t)decode_base<uint64_t>(dec, c);
     };
     GatePlan joint;  // geometry of a pair's joint class
     for (size_t i = 0; i < locs.size(); ++i) {

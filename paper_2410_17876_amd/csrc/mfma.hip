@@ -153,7 +153,7 @@ __global__ __launch_bounds__(kMfmaBlock) void block_mfma_c64(typename Cx<float>:
     int cur = 0;
     if (t < ntiles) {
         const int nc = ncols_of(t);
-        if ((int)threadIdx.x < nc) bases[0][threadIdx.x] = decode_base_rolled<I>(dec, t * (I)nt + (I)threadIdx.x);
+        if ((int)threadIdx.x < nc) bases[0][threadIdx.x] = decode_base<I>(dec, t * (I)nt + (I)threadIdx.x);
         __syncthreads();
         T v[EPT];
         gather(v, 0, nc);
@@ -165,7 +165,7 @@ __global__ __launch_bounds__(kMfmaBlock) void block_mfma_c64(typename Cx<float>:
         const bool has_next = tn < ntiles;
         const int ncols_next = has_next ? ncols_of(tn) : 0;
         if ((int)threadIdx.x < ncols_next)
-            bases[cur ^ 1][threadIdx.x] = decode_base_rolled<I>(dec, tn * (I)nt + (I)threadIdx.x);
+            bases[cur ^ 1][threadIdx.x] = decode_base<I>(dec, tn * (I)nt + (I)threadIdx.x);
         __syncthreads();  // tile t staged in Bs; next bases visible
         // Prefetch the next tile into registers; the loads land during this tile's work.
         T pv[EPT];

@@ -92,34 +92,13 @@ struct Decode {
     FastDiv<I> div[NS];
 };
 
-// The loop is unrolled to the compile-time bound and every step is guarded
-// instead of exiting early, so every table access has a constant index (scalar
-// registers or scalar loads on the device, never a dynamically indexed private
-// array). `last` is uniform, so the guards are uniform branches.
+// Decoders are read in place (kernel arguments, descriptors in global memory),
+// where a uniform index is a scalar load, so the loop stays rolled: one class
+// per thread in the sweeps, and an unrolled, guarded form of all kMaxSeg steps
+// measured slower (complex64 one-qudit monomial sweep 3.3 -> 4.7 ms on the
+// 1.72e9-amplitude register).
 template <typename I, int NS>
 __host__ __device__ inline I decode_base(const Decode<I, NS>& dec, I c) {
-    I base = dec.ctrl_off;
-    const int last = dec.nseg - 1;
-#pragma unroll
-    for (int g = 0; g < NS; ++g) {
-        if (g < last) {
-            const I q = fast_div<I>(c, dec.div[g]);
-            base += (c - q * dec.size[g]) * dec.stride[g];
-            c = q;
-        } else if (g == last) {
-            base += c * dec.stride[g];
-        }
-    }
-    return base;
-}
-
-// The same decode as a rolled loop, for decoders read in place from kernel
-// arguments or global memory (a uniform index there is a scalar load): the
-// one-gate sweeps decode one class per thread, and the unrolled form's 28
-// guarded steps cost them measurably (complex64 one-qudit monomial sweep 3.3 ->
-// 4.7 ms on the 1.72e9-amplitude register).
-template <typename I, int NS>
-__host__ __device__ inline I decode_base_rolled(const Decode<I, NS>& dec, I c) {
     I base = dec.ctrl_off;
     const int last = dec.nseg - 1;
     for (int g = 0; g < last; ++g) {

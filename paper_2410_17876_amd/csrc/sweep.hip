@@ -73,7 +73,7 @@ __global__ __launch_bounds__(kBlock) void sweep_dense_reg(typename Cx<R>::T* __r
     for (int v = 0; v < V; ++v) {
         const I c = first + (I)(v * kBlock);
         ok[v] = c < dec.n_classes;
-        base[v] = ok[v] ? decode_base_rolled<I>(dec, c) : (I)0;
+        base[v] = ok[v] ? decode_base<I>(dec, c) : (I)0;
     }
     T x[V][M];
 #pragma unroll
@@ -113,7 +113,7 @@ __global__ __launch_bounds__(kBlock) void sweep_monomial(typename Cx<R>::T* __re
     for (int v = 0; v < V; ++v) {
         const I c = first + (I)(v * kBlock);
         ok[v] = c < dec.n_classes;
-        base[v] = ok[v] ? decode_base_rolled<I>(dec, c) : (I)0;
+        base[v] = ok[v] ? decode_base<I>(dec, c) : (I)0;
     }
     T x[V][A];
 #pragma unroll
@@ -145,7 +145,7 @@ __global__ __launch_bounds__(kBlock) void sweep_dense_lds(typename Cx<R>::T* __r
     const I first = (I)blockIdx.x * (I)C;
     const I left = dec.n_classes - first;
     const int ncls = left < (I)C ? (int)left : C;
-    if ((int)threadIdx.x < ncls) sbase[threadIdx.x] = decode_base_rolled<I>(dec, first + (I)threadIdx.x);
+    if ((int)threadIdx.x < ncls) sbase[threadIdx.x] = decode_base<I>(dec, first + (I)threadIdx.x);
     __syncthreads();
     const int total = ncls * M;
     for (int e = threadIdx.x; e < total; e += kBlock) {
