@@ -17,13 +17,14 @@ enum Family { kFamIdentity = 0, kFamDenseReg = 1, kFamDenseLds = 2, kFamMonomial
 int plan_family(const GatePlan& p, int precision);
 const char* family_name(int family);
 
-// Matrix-core path (mfma.hip): dense complex64 gates with 17 <= M <= 128.
+// Matrix-core path (mfma.hip): dense gates with 17 <= M <= mfma_max_m(precision)
+// (128 for complex64 on FP32 MFMA, 64 for complex128 on FP64 MFMA).
 constexpr int kMfmaMinM = 17;
-constexpr int kMfmaMaxM = 128;
+int mfma_max_m(int precision);
 int mfma_padded(int M);
-size_t mfma_gate_bytes(int M, bool narrow);
-void fill_mfma_gate(const GatePlan& p, const double* U, void* dst);
-hipError_t launch_mfma(const GatePlan& p, void* psi, const void* dgate, hipStream_t stream);
+size_t mfma_gate_bytes(int M, bool narrow, int precision);
+void fill_mfma_gate(const GatePlan& p, int precision, const double* U, void* dst);
+hipError_t launch_mfma(const GatePlan& p, int precision, void* psi, const void* dgate, hipStream_t stream);
 
 // Bytes of device-side gate data (rounded U, member offsets) a plan needs, 0 if
 // everything travels in the kernel arguments.

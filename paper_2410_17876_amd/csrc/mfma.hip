@@ -1,4 +1,5 @@
-// mfma.hip - dense class updates on the matrix cores (complex64, 17 <= M <= 128).
+// mfma.hip - dense class updates on the matrix cores (complex64 with
+// 17 <= M <= 128 on FP32 MFMA, complex128 with 17 <= M <= 64 on FP64 MFMA).
 //
 // For a gate with a large class (several target qudits, e.g. a 25x25 or 125x125
 // block on ququints) the per-class update y = U x (paper Sec. 2.3) is a dense
@@ -10,14 +11,14 @@
 //
 // a real (2MP x 2MP) by (2MP x N) product with MP = M rounded up to 32, 64 or
 // 128 (padding rows and columns of the real matrix are zero). A workgroup has
-// eight wavefronts; each owns one 32-row block of the real matrix, kept in
-// registers for the whole launch (persistent workgroups loop over column
-// tiles), and one 32-column block of the tile. Per column tile the workgroup
-// gathers the classes' amplitudes into LDS (split into real and imaginary
-// rows), runs v_mfma_f32_32x32x2f32 over K = 2MP, writes the 32x32 result
-// blocks back to LDS and scatters them to the classes' addresses. A tile's
-// classes are read completely before any of them is written, and tiles are
-// disjoint, so the update is in place.
+// eight wavefronts; each owns one row block of the real matrix (32 rows for
+// v_mfma_f32_32x32x2f32, 16 for v_mfma_f64_16x16x4f64), kept in registers for
+// the whole launch (persistent workgroups loop over column tiles), and one or
+// more column blocks of the tile. Per column tile the workgroup gathers the
+// classes' amplitudes into LDS (split into real and imaginary rows), runs the
+// MFMAs over K = 2MP, writes the result blocks back to LDS and scatters them to
+// the classes' addresses. A tile's classes are read completely before any of
+// them is written, and tiles are disjoint, so the update is in place.
 //
 // Gather and scatter walk a tile's elements in address order: first the free
 // qudits below the lowest target (a run of F amplitudes; F = 1 when q0 is a
@@ -39,16 +40,40 @@
 namespace qd {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kMfmaBlock = 512;  // 8 wavefronts
 
+template <typename R, int MP>
+struct MfmaShape;
+
+// complex64, v_mfma_f32_32x32x2f32: a wavefront owns one 32-row block of the
+// real matrix and one 32-column block of the tile; K advances 2 per step.
 template <int MP>
-struct MfmaShape {
-    static constexpr int RB = 2 * MP / 32;  // 32-row blocks of the real matrix
-    static constexpr int NB = 8 / RB;       // 32-column blocks per tile
-    static constexpr int NT = 32 * NB;      // columns (classes) per tile
-    static constexpr int LOG_NT = NT == 128 ? 7 : (NT == 64 ? 6 : 5);
+struct MfmaShape<float, MP> {
+    static constexpr int RB = 2 * MP / 32;  // row blocks
+    static constexpr int NT = 32 * (8 / RB);
+    static constexpr int KS = MP;            // K steps
 };
+
+// complex128, v_mfma_f64_16x16x4f64: a wavefront owns one 16-row block and CB
+// 16-column blocks (CB independent accumulators); K advances 4 per step. The
+// real matrix must fit the eight wavefronts' registers: MP <= 64. Both sizes
+// tile 64 classes (MP = 32 with two column groups of two blocks, which keeps
+// the kernel within 128 VGPRs: two workgroups per CU).
+template <int MP>
+struct MfmaShape<double, MP> {
+    static_assert(MP <= 64, "complex128 matrix-core blocks hold at most 64 members");
+    static constexpr int RB = 2 * MP / 16;
+    static constexpr int CB = MP == 32 ? 2 : 4;
+    static constexpr int NT = 16 * CB * (8 / RB);
+    static constexpr int KS = MP / 2;
+};
+
+template <typename R, int MP>
+constexpr int mfma_log_nt() {
+    return MfmaShape<R, MP>::NT == 128 ? 7 : (MfmaShape<R, MP>::NT == 64 ? 6 : 5);
+}
 
 // Element order of a tile (see the header): F, inner and the classes per tile
 // nt (a multiple of F, at most NT), with their divisors; B = nt / F.
@@ -57,21 +82,23 @@ struct MfmaOrder {
     FastDiv<uint32_t> fdiv, idiv, bdiv;
 };
 
-template <int MP, typename I>
-__global__ __launch_bounds__(kMfmaBlock) void block_mfma_c64(typename Cx<float>::T* __restrict__ psi,
-                                                             const Decode<I> dec, const int M, const I ntiles,
-                                                             const float* __restrict__ A,
-                                                             const I* __restrict__ off,
-                                                             const int32_t* __restrict__ rmap_g,
-                                                             const MfmaOrder ord) {
-    using T = typename Cx<float>::T;
-    using S = MfmaShape<MP>;
+template <typename R, int MP, typename I>
+__global__ __launch_bounds__(kMfmaBlock) void block_mfma(typename Cx<R>::T* __restrict__ psi,
+                                                         const Decode<I> dec, const int M, const I ntiles,
+                                                         const R* __restrict__ A, const I* __restrict__ off,
+                                                         const int32_t* __restrict__ rmap_g,
+                                                         const MfmaOrder ord) {
+    using T = typename Cx<R>::T;
+    using S = MfmaShape<R, MP>;
+    constexpr bool kF32 = sizeof(R) == 4;
     constexpr int K2 = 2 * MP;
+    constexpr int LOG_NT = mfma_log_nt<R, MP>();
     constexpr int EPT = MP * S::NT / kMfmaBlock;  // tile elements gathered per thread
-    // 33 KB: real rows 0..MP-1, imaginary rows MP..2MP-1. One padding column, so
-    // that a wavefront writing down a column (low targets: consecutive lanes,
-    // consecutive rows) hits distinct banks.
-    __shared__ float Bs[K2][S::NT + 1];
+    // Real rows 0..MP-1, imaginary rows MP..2MP-1 (33 KB for complex64, 66 KB
+    // for complex128). One padding column, so that a wavefront writing down a
+    // column (low targets: consecutive lanes, consecutive rows) hits distinct
+    // banks.
+    __shared__ R Bs[K2][S::NT + 1];
     __shared__ I bases[2][S::NT];    // class bases of the current and the next tile
     __shared__ I offs[MP];
     __shared__ int32_t rmap[MP];
@@ -80,10 +107,17 @@ __global__ __launch_bounds__(kMfmaBlock) void block_mfma_c64(typename Cx<float>:
     const int wave = threadIdx.x >> 6;
     const int rb = wave % S::RB, cb = wave / S::RB;
 
-    // This wavefront's 32 rows of the real matrix, K = 2MP, two K values per step.
-    float a[MP];
+    // This wavefront's rows of the real matrix, all of K = 2MP, as MFMA A
+    // fragments: f32 32x32x2 lane l holds row l mod 32, K column 2s + l / 32;
+    // f64 16x16x4 lane l holds row l mod 16, K column 4s + l / 16.
+    R a[S::KS];
 #pragma unroll
-    for (int s = 0; s < MP; ++s) a[s] = A[(size_t)(32 * rb + (lane & 31)) * K2 + 2 * s + (lane >> 5)];
+    for (int s = 0; s < S::KS; ++s) {
+        if constexpr (kF32)
+            a[s] = A[(size_t)(32 * rb + (lane & 31)) * K2 + 2 * s + (lane >> 5)];
+        else
+            a[s] = A[(size_t)(16 * rb + (lane & 15)) * K2 + 4 * s + (lane >> 4)];
+    }
     for (int i = threadIdx.x; i < MP; i += kMfmaBlock) {
         offs[i] = i < M ? off[i] : (I)0;
         rmap[i] = i < M ? rmap_g[i] : 0;
@@ -91,7 +125,7 @@ __global__ __launch_bounds__(kMfmaBlock) void block_mfma_c64(typename Cx<float>:
     // Padding rows (M..MP-1) of the B tile are never gathered: zero them once
     // (the MFMA multiplies them by A's zero columns; they must be finite). The
     // write-back of the result keeps them zero (A's padding rows are zero).
-    for (int i = threadIdx.x; i < K2 * (S::NT + 1); i += kMfmaBlock) (&Bs[0][0])[i] = 0.0f;
+    for (int i = threadIdx.x; i < K2 * (S::NT + 1); i += kMfmaBlock) (&Bs[0][0])[i] = (R)0;
     __syncthreads();
     // Wait for the fragments once, here: left to the compiler, the wait for them
     // lands inside the tile loop, counted together with the prefetch loads, and
@@ -113,7 +147,7 @@ __global__ __launch_bounds__(kMfmaBlock) void block_mfma_c64(typename Cx<float>:
     auto element = [&](int e, int ncols, int* r, int* c) -> bool {
         if (ord.F == 1 && ord.inner == 1) {  // uniform: lanes over classes, then members
             *c = e & (S::NT - 1);
-            *r = e >> S::LOG_NT;
+            *r = e >> LOG_NT;
             return e < MN && *c < ncols;
         }
         const uint32_t q1 = fast_div<uint32_t>((uint32_t)e, ord.fdiv);
@@ -170,19 +204,48 @@ __global__ __launch_bounds__(kMfmaBlock) void block_mfma_c64(typename Cx<float>:
         // Prefetch the next tile into registers; the loads land during this tile's work.
         T pv[EPT];
         if (has_next) gather(pv, cur ^ 1, ncols_next);
-        f32x16 acc = {0};
+        if constexpr (kF32) {
+            f32x16 acc = {0};
 #pragma unroll
-        for (int s0 = 0; s0 < MP; s0 += 16) {
-            float b[16];
+            for (int s0 = 0; s0 < MP; s0 += 16) {
+                float b[16];
 #pragma unroll
-            for (int j = 0; j < 16; ++j) b[j] = Bs[2 * (s0 + j) + (lane >> 5)][32 * cb + (lane & 31)];
+                for (int j = 0; j < 16; ++j) b[j] = Bs[2 * (s0 + j) + (lane >> 5)][32 * cb + (lane & 31)];
 #pragma unroll
-            for (int j = 0; j < 16; ++j) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s0 + j], b[j], acc, 0, 0, 0);
+                for (int j = 0; j < 16; ++j) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s0 + j], b[j], acc, 0, 0, 0);
+            }
+            __syncthreads();  // every wavefront has read its B fragments
+            // 32x32x2 result: lane l, register r holds row 8 (r / 4) + 4 (l / 32) + r mod 4, column l mod 32.
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                Bs[32 * rb + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)][32 * cb + (lane & 31)] = acc[r];
+        } else {
+            constexpr int CB = S::CB;
+            f64x4 acc[CB];
+#pragma unroll
+            for (int c = 0; c < CB; ++c) acc[c] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s0 = 0; s0 < S::KS; s0 += 4) {
+                double b[4][CB];
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+#pragma unroll
+                    for (int c = 0; c < CB; ++c)
+                        b[j][c] = Bs[4 * (s0 + j) + (lane >> 4)][16 * (CB * cb + c) + (lane & 15)];
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+#pragma unroll
+                    for (int c = 0; c < CB; ++c)
+                        acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s0 + j], b[j][c], acc[c], 0, 0, 0);
+            }
+            __syncthreads();  // every wavefront has read its B fragments
+            // 16x16x4 result: lane l, register r holds row 4 r + l / 16, column l mod 16.
+#pragma unroll
+            for (int c = 0; c < CB; ++c)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    Bs[16 * rb + 4 * r + (lane >> 4)][16 * (CB * cb + c) + (lane & 15)] = acc[c][r];
         }
-        __syncthreads();  // every wavefront has read its B fragments
-#pragma unroll
-        for (int r = 0; r < 16; ++r)
-            Bs[32 * rb + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)][32 * cb + (lane & 31)] = acc[r];
         __syncthreads();
         for (int e = threadIdx.x; e < MN; e += kMfmaBlock) {
             int r = 0, c = 0;
@@ -201,9 +264,13 @@ __global__ __launch_bounds__(kMfmaBlock) void block_mfma_c64(typename Cx<float>:
 
 int mfma_padded(int M) { return M <= 32 ? 32 : (M <= 64 ? 64 : 128); }
 
-size_t mfma_gate_bytes(int M, bool narrow) {
+int mfma_max_m(int precision) { return precision == kC128 ? 64 : 128; }
+
+static size_t mfma_real_bytes(int precision) { return precision == kC128 ? sizeof(double) : sizeof(float); }
+
+size_t mfma_gate_bytes(int M, bool narrow, int precision) {
     const size_t K2 = 2 * (size_t)mfma_padded(M);
-    return K2 * K2 * sizeof(float) + (size_t)M * (narrow ? 4 : 8) + (size_t)M * 4;
+    return K2 * K2 * mfma_real_bytes(precision) + (size_t)M * (narrow ? 4 : 8) + (size_t)M * 4;
 }
 
 // The gather's element order (see the header), from the gate's free segments
@@ -244,26 +311,36 @@ static void mfma_rmap(const GatePlan& p, const Order& o, int32_t* rmap) {
     }
 }
 
-static int mfma_nt(int M) {
+static int mfma_nt(int M, int precision) {
     const int MP = mfma_padded(M);
-    return MP == 32 ? MfmaShape<32>::NT : (MP == 64 ? MfmaShape<64>::NT : MfmaShape<128>::NT);
+    if (precision == kC128) return MP == 32 ? MfmaShape<double, 32>::NT : MfmaShape<double, 64>::NT;
+    return MP == 32 ? MfmaShape<float, 32>::NT : (MP == 64 ? MfmaShape<float, 64>::NT : MfmaShape<float, 128>::NT);
 }
 
-void fill_mfma_gate(const GatePlan& p, const double* U, void* dst) {
+// The real form [[Ur, -Ui], [Ui, Ur]] of U, zero-padded to 2MP x 2MP, row-major.
+template <typename R>
+static void fill_real(const GatePlan& p, const double* U, R* A) {
     const int MP = mfma_padded(p.M);
     const int K2 = 2 * MP;
-    float* A = static_cast<float*>(dst);
-    for (int i = 0; i < K2 * K2; ++i) A[i] = 0.0f;
+    for (int i = 0; i < K2 * K2; ++i) A[i] = (R)0;
     for (int r = 0; r < p.M; ++r)
         for (int c = 0; c < p.M; ++c) {
-            const float ur = static_cast<float>(U[2 * (r * p.M + c)]);
-            const float ui = static_cast<float>(U[2 * (r * p.M + c) + 1]);
+            const R ur = static_cast<R>(U[2 * (r * p.M + c)]);
+            const R ui = static_cast<R>(U[2 * (r * p.M + c) + 1]);
             A[r * K2 + c] = ur;
             A[r * K2 + MP + c] = -ui;
             A[(MP + r) * K2 + c] = ui;
             A[(MP + r) * K2 + MP + c] = ur;
         }
-    unsigned char* o = static_cast<unsigned char*>(dst) + (size_t)K2 * K2 * sizeof(float);
+}
+
+void fill_mfma_gate(const GatePlan& p, int precision, const double* U, void* dst) {
+    const int K2 = 2 * mfma_padded(p.M);
+    if (precision == kC128)
+        fill_real<double>(p, U, static_cast<double*>(dst));
+    else
+        fill_real<float>(p, U, static_cast<float*>(dst));
+    unsigned char* o = static_cast<unsigned char*>(dst) + (size_t)K2 * K2 * mfma_real_bytes(precision);
     const bool narrow = p.D < (1ull << 31);
     if (narrow) {
         uint32_t* oo = reinterpret_cast<uint32_t*>(o);
@@ -273,12 +350,12 @@ void fill_mfma_gate(const GatePlan& p, const double* U, void* dst) {
         for (int a = 0; a < p.M; ++a) oo[a] = (uint64_t)p.off[a];
     }
     int32_t* rm = reinterpret_cast<int32_t*>(o + (size_t)p.M * (narrow ? 4 : 8));
-    mfma_rmap(p, mfma_order(p, mfma_nt(p.M)), rm);
+    mfma_rmap(p, mfma_order(p, mfma_nt(p.M, precision)), rm);
 }
 
-template <int MP, typename I>
+template <typename R, int MP, typename I>
 static hipError_t run_mfma(const GatePlan& p, void* psi, const void* dgate, hipStream_t st) {
-    using S = MfmaShape<MP>;
+    using S = MfmaShape<R, MP>;
     const Decode<I> dec = make_decode<I>(p);
     const Order o = mfma_order(p, S::NT);
     MfmaOrder ord;
@@ -297,29 +374,39 @@ static hipError_t run_mfma(const GatePlan& p, void* psi, const void* dgate, hipS
         hipError_t e = hipGetDevice(&dev);
         if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (e == hipSuccess)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, block_mfma_c64<MP, I>, kMfmaBlock, 0);
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, block_mfma<R, MP, I>, kMfmaBlock, 0);
         if (e != hipSuccess) return e;
         if (per_cu < 1) per_cu = 1;
     }
     const uint64_t grid = std::min<uint64_t>(ntiles, (uint64_t)per_cu * cus);
-    const float* A = static_cast<const float*>(dgate);
+    const R* A = static_cast<const R*>(dgate);
     const I* off = reinterpret_cast<const I*>(static_cast<const unsigned char*>(dgate) +
-                                              (size_t)(2 * MP) * (2 * MP) * sizeof(float));
+                                              (size_t)(2 * MP) * (2 * MP) * sizeof(R));
     const int32_t* rmap = reinterpret_cast<const int32_t*>(off + p.M);
-    hipLaunchKernelGGL((block_mfma_c64<MP, I>), dim3((unsigned)grid), dim3(kMfmaBlock), 0, st,
-                       static_cast<typename Cx<float>::T*>(psi), dec, p.M, (I)ntiles, A, off, rmap, ord);
+    hipLaunchKernelGGL((block_mfma<R, MP, I>), dim3((unsigned)grid), dim3(kMfmaBlock), 0, st,
+                       static_cast<typename Cx<R>::T*>(psi), dec, p.M, (I)ntiles, A, off, rmap, ord);
     return hipGetLastError();
 }
 
-hipError_t launch_mfma(const GatePlan& p, void* psi, const void* dgate, hipStream_t st) {
-    if (p.n_classes == 0) return hipSuccess;
-    const bool narrow = p.D < (1ull << 31);
-    switch (mfma_padded(p.M)) {
-        case 32: return narrow ? run_mfma<32, uint32_t>(p, psi, dgate, st) : run_mfma<32, uint64_t>(p, psi, dgate, st);
-        case 64: return narrow ? run_mfma<64, uint32_t>(p, psi, dgate, st) : run_mfma<64, uint64_t>(p, psi, dgate, st);
-        default:
-            return narrow ? run_mfma<128, uint32_t>(p, psi, dgate, st) : run_mfma<128, uint64_t>(p, psi, dgate, st);
+template <typename I>
+static hipError_t launch_mfma_typed(const GatePlan& p, int precision, void* psi, const void* dgate,
+                                    hipStream_t st) {
+    const int MP = mfma_padded(p.M);
+    if (precision == kC128) {
+        if (MP == 32) return run_mfma<double, 32, I>(p, psi, dgate, st);
+        if (MP == 64) return run_mfma<double, 64, I>(p, psi, dgate, st);
+        return hipErrorInvalidValue;  // the planner sends complex128 blocks above 64 members to the LDS sweep
     }
+    if (MP == 32) return run_mfma<float, 32, I>(p, psi, dgate, st);
+    if (MP == 64) return run_mfma<float, 64, I>(p, psi, dgate, st);
+    return run_mfma<float, 128, I>(p, psi, dgate, st);
+}
+
+hipError_t launch_mfma(const GatePlan& p, int precision, void* psi, const void* dgate, hipStream_t st) {
+    if (p.n_classes == 0) return hipSuccess;
+    if (p.M > mfma_max_m(precision)) return hipErrorInvalidValue;
+    return p.D < (1ull << 31) ? launch_mfma_typed<uint32_t>(p, precision, psi, dgate, st)
+                              : launch_mfma_typed<uint64_t>(p, precision, psi, dgate, st);
 }
 
 }  // namespace qd

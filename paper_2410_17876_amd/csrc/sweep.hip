@@ -182,7 +182,7 @@ int plan_family(const GatePlan& p, int precision) {
     if (p.category == kIdentity) return kFamIdentity;
     if ((p.category == kMonomial || p.category == kDiagonal) && p.n_active <= kRegMaxM) return kFamMonomial;
     if (p.M <= kRegMaxM) return kFamDenseReg;
-    if (precision == kC64 && p.category == kDense && p.M >= kMfmaMinM && p.M <= kMfmaMaxM) return kFamMfma;
+    if (p.category == kDense && p.M >= kMfmaMinM && p.M <= mfma_max_m(precision)) return kFamMfma;
     return kFamDenseLds;
 }
 
@@ -206,7 +206,7 @@ static int lds_classes(int M, int precision) {
 
 size_t device_gate_bytes(const GatePlan& p, int precision) {
     const int f = plan_family(p, precision);
-    if (f == kFamMfma) return mfma_gate_bytes(p.M, use32(p));
+    if (f == kFamMfma) return mfma_gate_bytes(p.M, use32(p), precision);
     const size_t ab = amp_bytes(precision);
     if (f == kFamDenseReg && p.M > kInlineMaxM) return (size_t)p.M * p.M * ab;
     if (f == kFamDenseLds) return (size_t)p.M * p.M * ab + (size_t)p.M * 8;
@@ -221,7 +221,7 @@ static void round_u(const double* U, int M, R* dst) {
 void fill_device_gate(const GatePlan& p, int precision, const double* U, void* dst) {
     const int f = plan_family(p, precision);
     if (f == kFamMfma) {
-        fill_mfma_gate(p, U, dst);
+        fill_mfma_gate(p, precision, U, dst);
         return;
     }
     if (f != kFamDenseReg && f != kFamDenseLds) return;
@@ -328,7 +328,7 @@ static hipError_t launch_typed(const GatePlan& p, int precision, void* psi, cons
                                const void* dgate, hipStream_t st) {
     switch (plan_family(p, precision)) {
         case kFamIdentity: return hipSuccess;
-        case kFamMfma: return launch_mfma(p, psi, dgate, st);
+        case kFamMfma: return launch_mfma(p, precision, psi, dgate, st);
         case kFamMonomial: return dispatch_monomial<R, I>(p, psi, st);
         case kFamDenseReg: return dispatch_dense_reg<R, I>(p, psi, U, dgate, st);
         case kFamDenseLds: return run_dense_lds<R, I>(p, precision, psi, dgate, st);

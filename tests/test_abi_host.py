@@ -105,6 +105,11 @@ def test_gate_categories_from_zero_pattern():
     assert qd.gate_info([5, 5, 5, 2], [0, 1, 2], haar(125, rng), precision="c64")["kernel"] == "block_mfma"
     assert qd.gate_info([5, 5, 2], [0, 1], haar(25, rng), precision="c64")["kernel"] == "block_mfma"
     assert qd.gate_info([7, 7, 7], [0, 1, 2], haar(343, rng), precision="c64")["kernel"] == "sweep_dense_lds"
+    # complex128 takes the FP64 matrix cores up to M = 64 (the real matrix fits the registers)
+    assert qd.gate_info([5, 5, 2], [0, 1], haar(25, rng), precision="c128")["kernel"] == "block_mfma"
+    assert qd.gate_info([4, 4, 4, 2], [0, 1, 2], haar(64, rng), precision="c128")["kernel"] == "block_mfma"
+    assert qd.gate_info([6, 6, 2, 3], [0, 1, 2], haar(72, rng), precision="c128")["kernel"] == "sweep_dense_lds"
+    assert qd.gate_info([4, 4, 2], [0, 1], haar(16, rng), precision="c128")["kernel"] == "sweep_dense_reg"
 
 
 def _rand_case(rng):

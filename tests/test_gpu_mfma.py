@@ -1,8 +1,10 @@
-"""Matrix-core path (complex64 dense gates with 17 <= M <= 128) against the FP64
-oracle, and the ququint workload: 2- and 3-qudit Haar gates (25x25, 125x125).
+"""Matrix-core path (dense gates with 17 <= M <= 128 in complex64 on FP32 MFMA,
+17 <= M <= 64 in complex128 on FP64 MFMA) against the FP64 oracle, and the
+ququint workload: 2- and 3-qudit Haar gates (25x25, 125x125).
 
 Tolerance: complex64, max-abs <= 2e-5 and <= 1e-5 of the largest amplitude,
-per gate layer (a layer = one gate, as each gate is one launch here)."""
+per gate layer (a layer = one gate, as each gate is one launch here);
+complex128, max-abs <= 1e-12."""
 import math
 
 import numpy as np
@@ -43,20 +45,47 @@ CASES = [  # (dims, targets): M = 18, 25, 27, 36, 48, 49, 64, 100, 125, 126, 25,
 ]
 
 
-@pytest.mark.parametrize("dims,targets", CASES)
-def test_mfma_gate_vs_oracle(dims, targets):
+def _m(dims, targets):
+    return math.prod(dims[t] for t in targets)
+
+
+PCASES = [(d, t, "c64") for d, t in CASES] + [(d, t, "c128") for d, t in CASES if _m(d, t) <= 64]
+
+
+@pytest.mark.parametrize("dims,targets,precision", PCASES)
+def test_mfma_gate_vs_oracle(dims, targets, precision):
     rng = np.random.default_rng(sum(dims) * 7 + len(targets))
     D = math.prod(dims)
-    M = math.prod(dims[t] for t in targets)
-    assert qd().gate_info(dims, targets, haar(M, rng), precision="c64")["kernel"] == "block_mfma"
+    M = _m(dims, targets)
+    assert qd().gate_info(dims, targets, haar(M, rng), precision=precision)["kernel"] == "block_mfma"
     psi0 = rand_state(rng, D)
     U = haar(M, rng)
     rest = [q for q in range(len(dims)) if q not in targets]
+    start = round32(psi0) if precision == "c64" else psi0
     for controls, values in (((), ()), ((rest[-1],), (dims[rest[-1]] - 1,))):
-        st = qd().State(dims, "c64", init=None).set_amplitudes(psi0)
+        st = qd().State(dims, precision, init=None).set_amplitudes(psi0)
         st.apply(targets, U, controls, values)
-        ref = oracle.apply(dims, round32(psi0), targets, U, controls, values)
-        assert_close(st.amplitudes(), ref, "c64", f"M={M} controls={controls}")
+        ref = oracle.apply(dims, start.copy(), targets, U, controls, values)  # in place: on a copy
+        assert_close(st.amplitudes(), ref, precision, f"M={M} controls={controls}")
+
+
+def test_mfma_c128_roundtrip_and_determinism():
+    # FP64 matrix cores: 64x64 (three ququarts) and 25x25 (two ququints) blocks,
+    # with ragged last tiles (D / M classes is no multiple of the tile width)
+    rng = np.random.default_rng(9)
+    dims = [4, 5, 4, 5, 4, 3, 2]
+    psi0 = rand_state(rng, math.prod(dims))
+    gates = [Gate((4, 0, 2), haar(64, rng)), Gate((1, 3), haar(25, rng)), Gate((3, 1), haar(25, rng)),
+             Gate((2, 4, 0), haar(64, rng)), Gate((0, 2, 4), haar(64, rng), (5,), (2,))]
+    for g in gates:
+        assert qd().gate_info(dims, g.targets, g.U, precision="c128")["kernel"] == "block_mfma"
+    a = qd().State(dims, "c128", init=None).set_amplitudes(psi0).run(gates)
+    b = qd().State(dims, "c128", init=None).set_amplitudes(psi0).run(gates)
+    assert np.array_equal(a.amplitudes(), b.amplitudes())
+    assert_close(a.amplitudes(), oracle.run(dims, gates, psi0.copy()), "c128", "5 gates")
+    for g in reversed(gates):
+        a.apply_gate(g.inverse())
+    assert_close(a.amplitudes(), psi0, "c128", "roundtrip")
 
 
 def test_mfma_roundtrip_and_determinism():
@@ -107,6 +136,31 @@ def test_64bit_path_mfma():
         want = oracle.apply_sampled(dims, g, idx, states.labelled_at)
         got = gpu_values(st, idx)
         assert np.max(np.abs(got - want)) <= 1e-5 * np.max(np.abs(want)), targets
+        st.apply_gate(g.inverse())
+    st.close()
+    del st
+    torch.cuda.empty_cache()
+
+
+def test_64bit_path_mfma_c128():
+    # D = 5^13 x 2 >= 2^31 in complex128 (39 GB): 64-bit class bases and offsets
+    import torch
+
+    dims = [5] * 13 + [2]
+    D = math.prod(dims)
+    st = qd().State(dims, "c128", init=None)
+    upload_chunks(st, lambda s, c: states.labelled(s, c), chunk=1 << 24)
+    rng = np.random.default_rng(12)
+    idx = np.concatenate([rng.integers(0, D, size=3000), [0, D - 1]])
+    for targets in ((12, 3), (0, 13, 6)):
+        M = math.prod(dims[t] for t in targets)
+        g = Gate(targets, haar(M, rng))
+        assert qd().gate_info(dims, targets, g.U, precision="c128")["kernel"] == "block_mfma"
+        st.apply_gate(g)
+        want = oracle.apply_sampled(dims, g, idx, states.labelled_at)
+        # labelled amplitudes reach 2^20: bound the error relative to the largest
+        err = float(np.max(np.abs(gpu_values(st, idx) - want)))
+        assert err <= 1e-13 * float(np.max(np.abs(want))), (targets, err)
         st.apply_gate(g.inverse())
     st.close()
     del st
