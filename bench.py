@@ -6,12 +6,15 @@ q_0..q_13 qubits, q_14..q_21 qutrits, q_22..q_23 ququads), a normalised complex
 Gaussian initial state (seed 1001) resident in HBM, and a 500-gate circuit: w.p.
 0.1 a 2-qudit Haar unitary, else the basic mix (1-qudit Haar 60%, DFT/X/Z 20%,
 controlled X 20%). One step = the whole circuit applied once, then the FP64
-norm. Four runs of the same circuit:
+norm. Six runs of the same circuit:
 
-  fused c128   qd_apply_circuit with LDS-staged fusion (the library's default
-               circuit path) -- the headline `value`
-  plain c128   one sweep per gate (qd_apply_gate)
-  fused c64, plain c64
+  lookahead c128  qd_apply_circuit with LDS-staged fusion and a 128-gate
+                  commuting look-ahead (a pass also takes later gates that
+                  commute with the ones it skips) -- the headline `value`
+  fused c128      the same passes strictly in the given order (the library's
+                  default circuit path)
+  plain c128      one sweep per gate (qd_apply_gate)
+  the same three in c64
 
 Metric: gate-amplitude updates/s = sum over gates of the amplitudes each gate
 changes (identity rows of U skipped; only classes whose controls hold) / wall
@@ -82,6 +85,9 @@ def load_traffic(kernel: str):
 
 
 TILE = {"c128": 0, "c64": 0}
+# Look-ahead of the planner in "lookahead" mode: a pass also takes later gates
+# that commute with the ones it skips (qd_circuit_options.reorder).
+LOOKAHEAD = 128
 
 
 def build_units(qd, dims, gates, precision, mode):
@@ -96,11 +102,14 @@ def build_units(qd, dims, gates, precision, mode):
                 continue
             units.append((kernel_key(info, precision), info["bytes"], info["updated"], ("gate", g), info["flops"]))
         return units
-    plan = qd.circuit_plan(dims, gates, precision, tile_amps=TILE[precision])
+    reorder = LOOKAHEAD if mode == "lookahead" else 0  # LOOKAHEAD: set from --lookahead
+    plan, order = qd.circuit_plan(dims, gates, precision, tile_amps=TILE[precision], reorder=reorder,
+                                  with_order=True)
     live = [i for i, info in enumerate(infos) if info["kernel"] != "identity"]
+    assert sorted(order) == live
     pos = 0
     for ngates, tile in plan:
-        idx = live[pos:pos + ngates]
+        idx = order[pos:pos + ngates]  # each pass's gates in the planned order
         pos += ngates
         upd = sum(infos[i]["updated"] for i in idx)
         if tile:
@@ -206,9 +215,10 @@ def run_precision(qd, dims, gates, precision, upload, steps, warmup, modes):
     return out
 
 
-def run_batched(qd, precision, steps, warmup, tune_cache):
+def run_batched(qd, precision, steps, warmup, tune_cache, lookahead):
     """The batched workload: 512 independent circuits (6..16 qudits, d in 2..5,
-    D <= 1e6, depth 100..1000, |0..0>) advanced together by qd_batch_apply."""
+    D <= 1e6, depth 100..1000, |0..0>) advanced together by qd_batch_apply,
+    passes planned with the given commuting look-ahead."""
     import torch
     from qd_inputs import circuits
 
@@ -226,11 +236,12 @@ def run_batched(qd, precision, steps, warmup, tune_cache):
 
     def trial(tile, run_len):
         if (tile, run_len) not in sample_plans:
-            sample_plans[(tile, run_len)] = sample.compile(sample_lists, tile_amps=tile, min_run=run_len)
+            sample_plans[(tile, run_len)] = sample.compile(sample_lists, tile_amps=tile, min_run=run_len,
+                                                           reorder=lookahead)
         sample_plans[(tile, run_len)].run(graph=True)
         torch.cuda.synchronize()
 
-    tuned = qd.tune.tune(trial, precision, "batched-workload-v2", tune_cache)
+    tuned = qd.tune.tune(trial, precision, f"batched-workload-v3-lookahead{lookahead}", tune_cache)
     for p in sample_plans.values():
         p.close()
     sample.close()
@@ -243,10 +254,10 @@ def run_batched(qd, precision, steps, warmup, tune_cache):
     for s, gl in zip(specs, lists):
         infos = [qd.gate_info(s.dims, g.targets, g.U, g.controls, g.values, precision) for g in gl.gates]
         updates += sum(i["updated"] for i in infos)
-        npass = len(qd.circuit_plan(s.dims, gl, precision, tile_amps=tile, min_run=run_len))
+        npass = len(qd.circuit_plan(s.dims, gl, precision, tile_amps=tile, min_run=run_len, reorder=lookahead))
         pass_bytes += npass * 2 * s.D * ab
     t0 = time.time()
-    plan = runner.compile(lists, tile_amps=tile, min_run=run_len)
+    plan = runner.compile(lists, tile_amps=tile, min_run=run_len, reorder=lookahead)
     log(f"batched {precision}: compiled {plan.rounds} rounds, {plan.items} items in {time.time() - t0:.1f} s")
     timing = {}
     for mode in ("eager", "graph"):
@@ -271,6 +282,7 @@ def run_batched(qd, precision, steps, warmup, tune_cache):
             "ms_per_step": 1e3 * wall / steps, "ms_per_step_eager_launches": 1e3 * timing["eager"] / steps,
             "launch_rounds_per_step": rounds, "items_per_step": items,
             "path": "compiled batch replayed as one hipGraph per step",
+            "lookahead": lookahead,
             "autotuned": {"tile_amps": tile, "min_run": run_len, "timings_s": tuned.get("timings_s")},
             "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                          "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": None, "kernel": "batch_tile",
@@ -347,12 +359,16 @@ def cpu_baseline(qd, dims, gates, psi, seconds):
 
 
 def main() -> int:
+    global LOOKAHEAD
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--gates", type=int, default=500)
-    ap.add_argument("--modes", default="fused,plain", help="comma list of fused, plain")
+    ap.add_argument("--modes", default="lookahead,fused,plain",
+                    help="comma list of lookahead (fused passes, commuting look-ahead), fused (in order), plain")
+    ap.add_argument("--lookahead", type=int, default=LOOKAHEAD,
+                    help="look-ahead in gates for lookahead mode and the batched runs (0 = in order)")
     ap.add_argument("--no-c64", action="store_true", help="skip the complex64 runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ququint", action="store_true", help="skip the 12-ququint MFMA workload")
@@ -390,6 +406,7 @@ def main() -> int:
     G = states.GaussianState(D, seed=circuits.SEEDS["large"])
     modes = [m for m in args.modes.split(",") if m]
     TILE["c128"], TILE["c64"] = args.tile_c128, args.tile_c64
+    LOOKAHEAD = args.lookahead
     t0 = time.time()
     host = None
     if not args.no_cpu_baseline:
@@ -419,7 +436,7 @@ def main() -> int:
         torch.cuda.empty_cache()
     if not args.no_batched:
         for p in (["c64", "c128"] if not args.no_c64 else ["c128"]):
-            res[f"batched_{p}"] = run_batched(qd, p, args.steps, args.warmup, args.tune_cache)
+            res[f"batched_{p}"] = run_batched(qd, p, args.steps, args.warmup, args.tune_cache, args.lookahead)
     if not args.no_served:
         res["served"] = run_served(qd, args.served_closed, args.served_open,
                                    [float(x) for x in args.served_loads.split(",")])
@@ -446,7 +463,8 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": workload, "D": D, "gates": len(gates), "precision": "c128", "path": head_mode},
+        "config": {"workload": workload, "D": D, "gates": len(gates), "precision": "c128", "path": head_mode,
+                   "lookahead": LOOKAHEAD if head_mode == "lookahead" else 0},
         "roofline": h["roofline"],
         "cpu_baseline": cpu,
         "copy_ceiling_GBps": {p: res[p]["copy_ceiling_GBps"] for p in ("c128", "c64") if p in res},

@@ -174,6 +174,9 @@ typedef struct {
     int32_t tile_amps;    /* largest tile of a fused pass in amplitudes; 0 = 4096 (c128) / 8192 (c64);
                              at most 32768 and at most 160 KB of LDS */
     int32_t min_run;      /* contiguous run a tile must hold, in amplitudes; 0 = 64 (c128) / 128 (c64) */
+    int32_t reorder;      /* look-ahead for commuting gates, in gates; 0 (default): strictly in order.
+                             With reorder > 0 a pass may also take a later gate that commutes with every
+                             gate it skips (see qd_apply_circuit); must not be negative */
     int32_t passes;       /* out: HBM passes enqueued */
     int32_t fused_passes; /* out: how many of them were fused passes */
 } qd_circuit_options;
@@ -186,15 +189,27 @@ typedef struct {
  * applies the gates of the run in order with the same per-class arithmetic as
  * qd_apply_gate, and writes it back once (Sec. 2.3: each gate maps every class,
  * hence every tile, to itself). The result is bitwise the same as applying the
- * gates one by one. Gates are never reordered. opts may be null. */
+ * gates one by one. With opts->reorder = 0 (and with opts null) gates are never
+ * reordered. With opts->reorder = w > 0, a gate that does not fit the open pass
+ * is skipped, and a gate up to w places after the first skipped one still joins
+ * the pass if it commutes with every skipped gate: its targets meet none of
+ * their targets or controls, and its controls meet none of their targets (the
+ * operators act on disjoint qudits or share only control qudits, so they
+ * commute exactly). The result is then bitwise that of applying the gates one
+ * by one in the planned order (qd_circuit_plan's `order`), which equals the
+ * given order's result up to rounding. opts may be null. */
 int qd_apply_circuit(qd_state* s, const qd_gate_desc* gates, int32_t count, qd_circuit_options* opts);
 
 /* Host-only: the passes qd_apply_circuit would enqueue for this register and
  * gate list. pass_gates[i] = gates in pass i, pass_tile[i] = tile amplitudes of
- * a fused pass or 0 for a one-gate sweep; both may be null, else they need room
- * for `count` entries. *npasses receives the number of passes. */
+ * a fused pass or 0 for a one-gate sweep; order receives the indices of the
+ * applied gates in the order they are applied, pass by pass (identity gates
+ * are dropped: the entries number the sum of pass_gates). All three may be
+ * null, else they need room for `count` entries. *npasses receives the number
+ * of passes. */
 int qd_circuit_plan(const int32_t* dims, int32_t n, int32_t precision, const qd_gate_desc* gates, int32_t count,
-                    const qd_circuit_options* opts, int32_t* pass_gates, int32_t* pass_tile, int32_t* npasses);
+                    const qd_circuit_options* opts, int32_t* pass_gates, int32_t* pass_tile, int32_t* order,
+                    int32_t* npasses);
 
 /* ---- batches of independent states ---------------------------------------------- */
 

@@ -24,18 +24,18 @@ class BatchRunner:
         for st in self.states:
             st.reset(0)
 
-    def run(self, gate_lists: Sequence, tile_amps: int = 0, min_run: int = 0) -> dict:
+    def run(self, gate_lists: Sequence, tile_amps: int = 0, min_run: int = 0, reorder: int = 0) -> dict:
         """Apply gate_lists[i] to state i; returns rounds/items and wall time (synchronised)."""
         gls = [g if isinstance(g, GateList) else GateList(g) for g in gate_lists]
         t0 = time.perf_counter()
-        info = self.batch.apply(self.states, gls, tile_amps=tile_amps, min_run=min_run)
+        info = self.batch.apply(self.states, gls, tile_amps=tile_amps, min_run=min_run, reorder=reorder)
         self.states[0].synchronize()
         info["seconds"] = time.perf_counter() - t0
         return info
 
-    def compile(self, gate_lists: Sequence, tile_amps: int = 0, min_run: int = 0) -> BatchPlan:
+    def compile(self, gate_lists: Sequence, tile_amps: int = 0, min_run: int = 0, reorder: int = 0) -> BatchPlan:
         """Plan and upload the rounds once; replay them with plan.run(graph=...)."""
-        return BatchPlan(self.states, gate_lists, tile_amps=tile_amps, min_run=min_run)
+        return BatchPlan(self.states, gate_lists, tile_amps=tile_amps, min_run=min_run, reorder=reorder)
 
     def updates(self, gate_lists) -> int:
         """Gate-amplitude updates of the gate lists (as counted per gate by the library)."""

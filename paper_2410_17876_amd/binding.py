@@ -36,8 +36,8 @@ class GateDesc(C.Structure):
 
 
 class CircuitOptions(C.Structure):
-    _fields_ = [("fuse", C.c_int32), ("tile_amps", C.c_int32), ("min_run", C.c_int32), ("passes", C.c_int32),
-                ("fused_passes", C.c_int32)]
+    _fields_ = [("fuse", C.c_int32), ("tile_amps", C.c_int32), ("min_run", C.c_int32), ("reorder", C.c_int32),
+                ("passes", C.c_int32), ("fused_passes", C.c_int32)]
 
 
 class GateInfo(C.Structure):
@@ -79,7 +79,7 @@ def _load() -> C.CDLL:
         "qd_copy_ceiling": [vp, C.c_int32, f64p],
         "qd_apply_circuit": [vp, C.POINTER(GateDesc), C.c_int32, C.POINTER(CircuitOptions)],
         "qd_circuit_plan": [i32p, C.c_int32, C.c_int32, C.POINTER(GateDesc), C.c_int32, C.POINTER(CircuitOptions),
-                            i32p, i32p, i32p],
+                            i32p, i32p, i32p, i32p],
         "qd_batch_create": [C.c_int32, C.POINTER(vp)],
         "qd_batch_destroy": [vp],
         "qd_batch_apply": [vp, C.POINTER(vp), C.POINTER(C.POINTER(GateDesc)), i32p, C.c_int32,
@@ -159,23 +159,28 @@ class GateListView:
         return self.count
 
 
-def _options(fuse=True, tile_amps=0, min_run=0) -> CircuitOptions:
-    return CircuitOptions(1 if fuse else 0, int(tile_amps), int(min_run), 0, 0)
+def _options(fuse=True, tile_amps=0, min_run=0, reorder=0) -> CircuitOptions:
+    return CircuitOptions(1 if fuse else 0, int(tile_amps), int(min_run), int(reorder), 0, 0)
 
 
-def circuit_plan(dims, gates, precision="c128", fuse=True, tile_amps=0, min_run=0):
-    """Passes qd_apply_circuit would enqueue: list of (gates in pass, tile amplitudes or 0)."""
+def circuit_plan(dims, gates, precision="c128", fuse=True, tile_amps=0, min_run=0, reorder=0, with_order=False):
+    """Passes qd_apply_circuit would enqueue: list of (gates in pass, tile amplitudes or 0);
+    with_order: also the applied gates' indices in application order."""
     gl = gates if isinstance(gates, GateList) else GateList(gates)
     d, dp = _i32(dims)
     n = len(gl)
     pg = np.zeros(max(1, n), dtype=np.int32)
     pt = np.zeros(max(1, n), dtype=np.int32)
+    order = np.zeros(max(1, n), dtype=np.int32)
     npass = C.c_int32()
-    opts = _options(fuse, tile_amps, min_run)
+    opts = _options(fuse, tile_amps, min_run, reorder)
+    ptr = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32))
     check(lib.qd_circuit_plan(dp, len(dims), PRECISIONS[precision], gl.descs, n, C.byref(opts),
-                              pg.ctypes.data_as(C.POINTER(C.c_int32)), pt.ctypes.data_as(C.POINTER(C.c_int32)),
-                              C.byref(npass)))
-    return [(int(pg[i]), int(pt[i])) for i in range(npass.value)]
+                              ptr(pg), ptr(pt), ptr(order), C.byref(npass)))
+    passes = [(int(pg[i]), int(pt[i])) for i in range(npass.value)]
+    if with_order:
+        return passes, [int(x) for x in order[:sum(p[0] for p in passes)]]
+    return passes
 
 
 def dim(dims: Sequence[int]) -> int:
@@ -272,10 +277,10 @@ class State:
             self.apply_gate(g)
         return self
 
-    def run_circuit(self, gates, fuse=True, tile_amps=0, min_run=0) -> dict:
+    def run_circuit(self, gates, fuse=True, tile_amps=0, min_run=0, reorder=0) -> dict:
         """Apply a gate list through qd_apply_circuit; returns the pass counts."""
         gl = gates if isinstance(gates, GateList) else GateList(gates)
-        opts = _options(fuse, tile_amps, min_run)
+        opts = _options(fuse, tile_amps, min_run, reorder)
         check(lib.qd_apply_circuit(self._h, gl.descs, len(gl), C.byref(opts)))
         return {"passes": opts.passes, "fused_passes": opts.fused_passes}
 
@@ -352,11 +357,11 @@ def _batch_args(states, gate_lists):
 class BatchPlan:
     """A compiled batch (qd_batch_compile): replay the same gate lists on the states."""
 
-    def __init__(self, states, gate_lists, tile_amps=0, min_run=0):
+    def __init__(self, states, gate_lists, tile_amps=0, min_run=0, reorder=0):
         self.states = list(states)
         self._keep = _batch_args(self.states, gate_lists)
         gls, hs, gp, counts = self._keep
-        opts = _options(True, tile_amps, min_run)
+        opts = _options(True, tile_amps, min_run, reorder)
         self._h = C.c_void_p()
         check(lib.qd_batch_compile(hs, gp, counts.ctypes.data_as(C.POINTER(C.c_int32)), len(self.states),
                                    C.byref(opts), C.byref(self._h)))
@@ -385,11 +390,11 @@ class Batch:
         self._h = C.c_void_p()
         check(lib.qd_batch_create(self.precision, C.byref(self._h)))
 
-    def apply(self, states, gate_lists, tile_amps=0, min_run=0) -> dict:
+    def apply(self, states, gate_lists, tile_amps=0, min_run=0, reorder=0) -> dict:
         """Apply gate_lists[i] to states[i] for all i (qd_batch_apply)."""
         n = len(states)
         gls, hs, gp, counts = _batch_args(states, gate_lists)
-        opts = _options(True, tile_amps, min_run)
+        opts = _options(True, tile_amps, min_run, reorder)
         check(lib.qd_batch_apply(self._h, hs, gp, counts.ctypes.data_as(C.POINTER(C.c_int32)), n, C.byref(opts)))
         return {"rounds": opts.passes, "items": opts.fused_passes}
 

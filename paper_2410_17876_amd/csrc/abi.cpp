@@ -392,8 +392,10 @@ int circuit_options(const qd_circuit_options* o, int precision, CircuitOptions* 
     if (tile > 32768) return set_err(QD_ERR_INVALID_ARGUMENT, "tile_amps must be at most 32768");
     if (tile * amp_bytes(precision) > 160 * 1024)
         return set_err(QD_ERR_INVALID_ARGUMENT, "a tile must fit the 160 KB of LDS");
+    if (o && o->reorder < 0) return set_err(QD_ERR_INVALID_ARGUMENT, "reorder must not be negative");
     co->tile_max = tile;
     co->min_run = run;
+    co->reorder = o ? o->reorder : 0;
     return QD_OK;
 }
 
@@ -430,7 +432,8 @@ int qd_apply_gate(qd_state* s, const int32_t* targets, int32_t k, const int32_t*
 }
 
 int qd_circuit_plan(const int32_t* dims, int32_t n, int32_t precision, const qd_gate_desc* gates, int32_t count,
-                    const qd_circuit_options* opts, int32_t* pass_gates, int32_t* pass_tile, int32_t* npasses) {
+                    const qd_circuit_options* opts, int32_t* pass_gates, int32_t* pass_tile, int32_t* order,
+                    int32_t* npasses) {
     int rc = check_precision(precision);
     if (rc) return rc;
     std::string err;
@@ -447,9 +450,12 @@ int qd_circuit_plan(const int32_t* dims, int32_t n, int32_t precision, const qd_
     rc = plan_circuit(dims, n, precision, cg.data(), count, co, plan, &err);
     if (rc) return set_err(rc, err);
     *npasses = (int32_t)plan.size();
+    size_t k = 0;
     for (size_t i = 0; i < plan.size(); ++i) {
         if (pass_gates) pass_gates[i] = (int32_t)plan[i].gates.size();
         if (pass_tile) pass_tile[i] = plan[i].fused ? (int32_t)plan[i].launch.tile : 0;
+        if (order)
+            for (int g : plan[i].gates) order[k++] = g;
     }
     return QD_OK;
 }

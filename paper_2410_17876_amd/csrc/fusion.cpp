@@ -243,35 +243,93 @@ int plan_circuit(const int32_t* dims, int n, int precision, const CircuitGate* g
     int p_low = 0;
     while (p_low < n && s[p_low] < opt.min_run) ++p_low;
     const uint64_t tile_max = opt.tile_max;
-
-    GatePlan* gp = new GatePlan;
-    std::vector<int> cur;
-    bool inS[QD_MAX_QUDITS] = {false};
-    uint64_t prodS = 0;
     // Upper bound of the pass's device data (descriptor, class-base table of at
     // most tile / 2 classes, matrix): a pass must fit one staging slot.
     const uint64_t tile_bound = std::min<uint64_t>(tile_max, D);
-    size_t blob_est = 0;
-    auto gate_bytes = [&](const GatePlan& p) {
-        return sizeof(TileGate) + (size_t)tile_bound + (size_t)p.M * p.M * 16 + 64;
-    };
 
-    auto prod_with = [&](const CircuitGate& g) {
-        uint64_t pr = prodS;
-        for (int l = 0; l < g.k; ++l)
-            if (!inS[g.targets[l]]) pr *= (uint64_t)dims[g.targets[l]];
-        return pr;
+    // Every gate planned once: identity gates are dropped, the others noted with
+    // their fusability, device-data bound and qudit masks.
+    struct Info {
+        bool skip, can;
+        size_t bytes;
+        uint64_t tmask, cmask;
     };
-    auto open_pass = [&]() {
-        std::fill(inS, inS + n, false);
-        prodS = 1;
+    std::vector<Info> info(count);
+    {
+        GatePlan* gp = new GatePlan;
+        for (int i = 0; i < count && !rc; ++i) {
+            const CircuitGate& g = gates[i];
+            rc = plan_gate(dims, n, g.targets, g.k, g.controls, g.values, g.m, g.U, gp, err);
+            if (rc) break;
+            Info& f = info[i];
+            f.skip = gp->category == kIdentity;
+            f.can = opt.fuse && fusable(*gp, g.m);
+            f.bytes = sizeof(TileGate) + (size_t)tile_bound + (size_t)gp->M * gp->M * 16 + 64;
+            f.tmask = f.cmask = 0;
+            for (int l = 0; l < g.k; ++l) f.tmask |= 1ull << g.targets[l];
+            for (int l = 0; l < g.m; ++l) f.cmask |= 1ull << g.controls[l];
+        }
+        delete gp;
+    }
+    if (rc) return rc;
+
+    std::vector<char> done(count, 0);
+    for (int i = 0; i < count; ++i) done[i] = info[i].skip;
+    const uint64_t all = n >= 64 ? ~0ull : (1ull << n) - 1;
+    int first = 0;
+    while (true) {
+        while (first < count && done[first]) ++first;
+        if (first >= count) break;
+        // Open a pass on the low block and take gates in order while their
+        // targets fit the tile. With look-ahead, a gate that does not fit is
+        // skipped, and a later gate still joins if it commutes with every
+        // skipped gate: its targets meet none of their targets and controls, and
+        // its controls meet none of their targets (gates on disjoint qudits, or
+        // sharing only control qudits, commute). The scan ends `reorder` gates
+        // after the first skipped one, or once every qudit is blocked.
+        bool inS[QD_MAX_QUDITS] = {false};
+        uint64_t prodS = 1;
         for (int q = 0; q < p_low; ++q) {
             inS[q] = true;
             prodS *= (uint64_t)dims[q];
         }
-    };
-    auto close_pass = [&]() -> int {
-        if (cur.empty()) return QD_OK;
+        std::vector<int> cur;
+        size_t blob_est = 0;
+        uint64_t blockT = 0, blockA = 0;
+        int first_skip = -1;
+        for (int j = first; j < count; ++j) {
+            if (done[j]) continue;
+            if (first_skip >= 0 && j - first_skip > opt.reorder) break;
+            const CircuitGate& g = gates[j];
+            const Info& f = info[j];
+            uint64_t pr = prodS;
+            for (int l = 0; l < g.k; ++l)
+                if (!inS[g.targets[l]]) pr *= (uint64_t)dims[g.targets[l]];
+            const bool fits = f.can && pr <= tile_max && blob_est + f.bytes <= kPassBlobMax;
+            const bool commutes = !(f.tmask & blockA) && !(f.cmask & blockT);
+            if (fits && commutes) {
+                for (int l = 0; l < g.k; ++l) inS[g.targets[l]] = true;
+                prodS = pr;
+                cur.push_back(j);
+                blob_est += f.bytes;
+                done[j] = 1;
+                continue;
+            }
+            if (cur.empty()) {  // cannot start a pass (not fusable, or its targets alone exceed the tile)
+                PassPlan pp;
+                pp.fused = false;
+                pp.gates = {j};
+                out.push_back(std::move(pp));
+                done[j] = 1;
+                break;
+            }
+            if (opt.reorder <= 0) break;
+            if (first_skip < 0) first_skip = j;
+            blockT |= f.tmask;
+            blockA |= f.tmask | f.cmask;
+            if ((blockA & all) == all) break;
+        }
+        if (cur.empty()) continue;
         PassPlan pp;
         if (cur.size() == 1 && !opt.single_as_fused) {
             pp.fused = false;
@@ -287,52 +345,11 @@ int plan_circuit(const int32_t* dims, int n, int precision, const CircuitGate* g
             std::vector<int> S;
             for (int q = 0; q < n; ++q)
                 if (inS[q]) S.push_back(q);
-            int r2 = build_fused(dims, n, precision, gates, cur, S, p_low, &pp, err);
-            if (r2) return r2;
+            rc = build_fused(dims, n, precision, gates, cur, S, p_low, &pp, err);
+            if (rc) break;
         }
-        out.push_back(std::move(pp));
-        cur.clear();
-        return QD_OK;
-    };
-
-    for (int i = 0; i < count; ++i) {
-        const CircuitGate& g = gates[i];
-        rc = plan_gate(dims, n, g.targets, g.k, g.controls, g.values, g.m, g.U, gp, err);
-        if (rc) break;
-        if (gp->category == kIdentity) continue;
-        const bool can = opt.fuse && fusable(*gp, g.m);
-        if (can && !cur.empty() && prod_with(g) <= tile_max && blob_est + gate_bytes(*gp) <= kPassBlobMax) {
-            for (int l = 0; l < g.k; ++l)
-                if (!inS[g.targets[l]]) {
-                    inS[g.targets[l]] = true;
-                    prodS *= (uint64_t)dims[g.targets[l]];
-                }
-            cur.push_back(i);
-            blob_est += gate_bytes(*gp);
-            continue;
-        }
-        if ((rc = close_pass())) break;
-        blob_est = 0;
-        if (can) {
-            open_pass();
-            if (prod_with(g) <= tile_max) {
-                for (int l = 0; l < g.k; ++l)
-                    if (!inS[g.targets[l]]) {
-                        inS[g.targets[l]] = true;
-                        prodS *= (uint64_t)dims[g.targets[l]];
-                    }
-                cur.push_back(i);
-                blob_est += gate_bytes(*gp);
-                continue;
-            }
-        }
-        PassPlan pp;
-        pp.fused = false;
-        pp.gates = {i};
         out.push_back(std::move(pp));
     }
-    if (!rc) rc = close_pass();
-    delete gp;
     if (rc) out.clear();
     return rc;
 }

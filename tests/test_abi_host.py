@@ -177,6 +177,74 @@ def test_circuit_plan_partitions_gates_in_order():
     assert qd.circuit_plan(dims, gates, "c128") == [(len(gates), 144)]
 
 
+def _commute(a, b):
+    # operators on disjoint qudits, or sharing only control qudits, commute
+    ta, tb = set(a.targets), set(b.targets)
+    return not (ta & (tb | set(b.controls))) and not (tb & set(a.controls))
+
+
+def _random_controlled(rng, dims, count):
+    from qd_inputs import Gate
+    n, out = len(dims), []
+    while len(out) < count:
+        k = int(rng.integers(1, 3))
+        t = [int(x) for x in rng.choice(n, k, replace=False)]
+        M = math.prod(dims[x] for x in t)
+        rest = [q for q in range(n) if q not in t]
+        m = int(rng.integers(0, 3))
+        c = [int(x) for x in rng.choice(rest, m, replace=False)]
+        U = haar(M, rng) if M <= 16 or rng.random() < 0.1 else (shift(M) if rng.random() < 0.5 else np.eye(M))
+        out.append(Gate(tuple(t), U, tuple(c), tuple(int(rng.integers(dims[x])) for x in c)))
+    return out
+
+
+@pytest.mark.parametrize("reorder", [0, 4, 32, 1000])
+def test_circuit_plan_reorders_only_commuting_gates(reorder):
+    from qd_inputs import circuits
+    rng = np.random.default_rng(reorder)
+    cases = [circuits.large(), circuits.plain(), ([2, 3, 2, 4, 3, 2, 5, 2], _random_controlled(rng, [2, 3, 2, 4, 3, 2, 5, 2], 300))]
+    for dims, gates in cases:
+        for prec in ("c128", "c64"):
+            plan, order = qd.circuit_plan(dims, gates, prec, reorder=reorder, with_order=True, tile_amps=512)
+            kept = [i for i, g in enumerate(gates) if not np.array_equal(g.U, np.eye(len(g.U)))]
+            assert sorted(order) == kept  # every non-identity gate exactly once
+            if reorder == 0:
+                assert order == kept
+            pos = {g: p for p, g in enumerate(order)}
+            for i in kept:
+                for j in kept:
+                    if i < j and pos[j] < pos[i]:
+                        assert _commute(gates[i], gates[j]), (i, j)
+            # the passes partition the order
+            assert sum(g for g, _ in plan) == len(order)
+    # look-ahead fills passes: fewer of them on the large register
+    dims, gates = circuits.large()
+    n0 = len(qd.circuit_plan(dims, gates, "c128"))
+    n1 = len(qd.circuit_plan(dims, gates, "c128", reorder=128))
+    assert n1 < n0 * 0.5, (n0, n1)
+
+
+def test_reordered_plan_gives_the_same_state_in_the_oracle():
+    # the planned order is a reordering of commuting operators: the FP64 oracle
+    # reaches the same state (to rounding) as in the given order
+    rng = np.random.default_rng(8)
+    dims = [2, 3, 2, 4, 3, 2, 5]
+    gates = _random_controlled(rng, dims, 120)
+    _, order = qd.circuit_plan(dims, gates, "c128", reorder=64, tile_amps=256, with_order=True)
+    assert order != sorted(order)  # something did move
+    v = rng.standard_normal(math.prod(dims)) + 1j * rng.standard_normal(math.prod(dims))
+    v /= np.linalg.norm(v)
+    a = oracle.run(dims, gates, v)
+    b = oracle.run(dims, [gates[i] for i in order], v)
+    assert np.max(np.abs(a - b)) < 1e-13
+
+
+def test_reorder_must_not_be_negative():
+    from qd_inputs import Gate
+    with pytest.raises(qd.QDError):
+        qd.circuit_plan([2, 2], [Gate((0,), np.eye(2))], reorder=-1)
+
+
 def test_circuit_plan_skips_identity_and_keeps_big_gates_alone():
     rng = np.random.default_rng(3)
     dims = [5, 5, 5, 2, 3]

@@ -1,6 +1,7 @@
 """LDS-staged fusion (qd_apply_circuit): the fused result must equal the
-one-sweep-per-gate result bit for bit (same per-class arithmetic, gates never
-reordered) and the FP64 oracle within the tolerances."""
+one-sweep-per-gate result bit for bit (same per-class arithmetic; in the given
+order, or with look-ahead in the planned order) and the FP64 oracle within the
+tolerances."""
 import math
 
 import numpy as np
@@ -73,6 +74,33 @@ def test_fused_equals_sequential_and_oracle(precision, case):
     for g in gates:
         oracle.apply_gate(dims, ref, g)
     assert_close(ga, ref, precision, f"fused {dims}")
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_reordered_passes_equal_planned_order_and_oracle(precision, case):
+    # With look-ahead the passes apply commuting gates out of the given order:
+    # bitwise the one-by-one result in the planned order, and the oracle's
+    # result in the given order within the tolerances.
+    dims, tile, run = CASES[case]
+    if precision == "c64":
+        tile *= 2
+    rng = np.random.default_rng(700 + case)
+    psi0 = rand_state(rng, math.prod(dims))
+    gates = mixed_gates(rng, dims, 80)
+    passes, order = qd().circuit_plan(dims, gates, precision, tile_amps=tile, min_run=run, reorder=64,
+                                      with_order=True)
+    a = qd().State(dims, precision, init=None).set_amplitudes(psi0)
+    info = a.run_circuit(gates, tile_amps=tile, min_run=run, reorder=64)
+    assert info["passes"] == len(passes)
+    c = qd().State(dims, precision, init=None).set_amplitudes(psi0)
+    c.run([gates[i] for i in order])
+    assert np.array_equal(a.amplitudes(), c.amplitudes())
+    ref = psi0.copy() if precision == "c128" else (psi0.real.astype(np.float32).astype(np.float64) +
+                                                   1j * psi0.imag.astype(np.float32).astype(np.float64))
+    for g in gates:
+        oracle.apply_gate(dims, ref, g)
+    assert_close(a.amplitudes(), ref, precision, f"reordered {dims}")
 
 
 @pytest.mark.parametrize("precision", ["c128", "c64"])
