@@ -171,7 +171,7 @@ typedef struct {
 typedef struct {
     int32_t fuse;         /* 1 (default when opts is null): LDS-staged fusion of consecutive gates;
                              0: one sweep per gate, exactly as qd_apply_gate */
-    int32_t tile_amps;    /* largest tile of a fused pass in amplitudes; 0 = 4096 (c128) / 8192 (c64);
+    int32_t tile_amps;    /* largest tile of a fused pass in amplitudes; 0 = 3072 (c128) / 8192 (c64);
                              at most 32768 and at most 160 KB of LDS */
     int32_t min_run;      /* contiguous run a tile must hold, in amplitudes; 0 = 64 (c128) / 128 (c64) */
     int32_t reorder;      /* look-ahead for commuting gates, in gates; 0 (default): strictly in order.

@@ -387,7 +387,7 @@ int enqueue_single(qd_state* s, const GatePlan& p, const double* U) {
 
 int circuit_options(const qd_circuit_options* o, int precision, CircuitOptions* co) {
     co->fuse = o ? o->fuse != 0 : true;
-    const uint64_t tile = (o && o->tile_amps > 0) ? (uint64_t)o->tile_amps : (precision == QD_C128 ? 4096 : 8192);
+    const uint64_t tile = (o && o->tile_amps > 0) ? (uint64_t)o->tile_amps : (precision == QD_C128 ? 3072 : 8192);
     const uint64_t run = (o && o->min_run > 0) ? (uint64_t)o->min_run : (precision == QD_C128 ? 64 : 128);
     if (tile > 32768) return set_err(QD_ERR_INVALID_ARGUMENT, "tile_amps must be at most 32768");
     if (tile * amp_bytes(precision) > 160 * 1024)

@@ -44,13 +44,24 @@ constexpr int kMaxOuterCtl = 8;     // controls outside S per gate
 constexpr int32_t kDensePair = 8;   // TileGate::kind of a pair (distinct from the Category values)
 constexpr int kPairMaxM = 4;
 
+// Consecutive dense gates with the same targets (in the same order) and the
+// same controls act on the same classes: a chain of them shares one
+// descriptor. A thread reads a class from LDS once, applies the gates one after
+// the other in registers (each row with the single-gate arithmetic) and writes
+// it back once: bitwise the gate-by-gate result, with one LDS round trip and
+// one barrier for the whole chain.
+constexpr int32_t kDenseChain = 9;  // TileGate::kind of a chain; M2 = its length, the matrices follow each other
+constexpr int kChainMaxM = 4;
+constexpr int kChainMaxLen = 16;
+
 struct TileGate {
-    int32_t kind;        // kDense, kDensePair, or kMonomial for monomial and diagonal gates
-    int32_t M;           // dense: class size; pair: class size of the first gate; monomial: active entries
-    int32_t M2;          // pair: class size of the second gate (its U follows the first's in the blob)
+    int32_t kind;        // kDense, kDensePair, kDenseChain, or kMonomial for monomial and diagonal gates
+    int32_t M;           // dense, chain: class size; pair: class size of the first gate; monomial: active entries
+    int32_t M2;          // pair: class size of the second gate (its U follows the first's in the blob);
+                         // chain: number of gates
     uint32_t n_classes;                 // classes of the gate inside one tile
     uint32_t bases_off;                 // byte offset of the uint16 class bases in the blob
-    uint32_t off[kFuseMaxM];            // dense, pair: member offsets; monomial: source offsets
+    uint32_t off[kFuseMaxM];            // dense, pair, chain: member offsets; monomial: source offsets
     uint32_t dst[kFuseMaxM];            // monomial: destination offsets
     uint32_t one_mask;                  // monomial: bit i set if factor i is exactly 1
     int32_t n_outer;                    // controls outside S

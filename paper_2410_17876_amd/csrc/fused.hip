@@ -5,8 +5,9 @@
 // the tile back. fused_tile serves a single state, batch_tile one tile of one
 // (state, pass) item of a batched round.
 //
-// Two workgroups share a CU (64 KB tiles), so one's loads and stores overlap the
-// other's LDS work. A persistent variant with one 512-thread workgroup per CU
+// Several workgroups share a CU (two 64 KB complex64 tiles; three 48 KB
+// complex128 tiles at the default 3072 amplitudes), so one's loads and stores
+// overlap the others' LDS work. A persistent variant with one 512-thread workgroup per CU
 // that prefetched the next tile into registers measured slower (the LDS phase
 // then has no other workgroup to hide its latency) and was dropped.
 #include <hip/hip_runtime.h>
@@ -258,6 +259,54 @@ __device__ __forceinline__ void tile_pair(typename Cx<R>::T* tile, const TileGat
     });
 }
 
+// A chain (kDenseChain in fused.h) on UF classes: n dense gates applied one
+// after the other in registers, every row with dense_row (the single-gate
+// arithmetic); only the last gate's rows go to LDS.
+template <typename R, int M, int UF>
+__device__ __forceinline__ void chain_classes(typename Cx<R>::T* tile, const typename Cx<R>::T* __restrict__ U,
+                                              const int n, const uint32_t (&off)[M], const uint32_t (&base)[UF],
+                                              const bool (&ok)[UF]) {
+    using T = typename Cx<R>::T;
+    T x[UF][M];
+#pragma unroll
+    for (int u = 0; u < UF; ++u)
+#pragma unroll
+        for (int a = 0; a < M; ++a) x[u][a] = ok[u] ? tile[base[u] + off[a]] : T{0, 0};
+#pragma unroll 1
+    for (int g = 0; g + 1 < n; ++g) {
+        const T* __restrict__ Ug = U + g * M * M;
+#pragma unroll
+        for (int u = 0; u < UF; ++u) {
+            T y[M];
+#pragma unroll
+            for (int r = 0; r < M; ++r) y[r] = dense_row<R, M>(x[u], [&](int i) { return Ug[i]; }, r);
+#pragma unroll
+            for (int r = 0; r < M; ++r) x[u][r] = y[r];
+        }
+    }
+    const T* __restrict__ Ul = U + (n - 1) * M * M;
+#pragma unroll
+    for (int u = 0; u < UF; ++u) {
+        if (!ok[u]) continue;
+#pragma unroll
+        for (int r = 0; r < M; ++r) tile[base[u] + off[r]] = dense_row<R, M>(x[u], [&](int i) { return Ul[i]; }, r);
+    }
+}
+
+template <typename R, int M, int BS>
+__device__ __forceinline__ void tile_chain(typename Cx<R>::T* tile, const TileGate* __restrict__ G,
+                                           const typename Cx<R>::T* __restrict__ U, const uint16_t* bases,
+                                           const uint32_t (&pre)[kPre]) {
+    constexpr int UF = class_unroll<2 * M>();  // x and the next gate's rows both live
+    uint32_t off[M];
+#pragma unroll
+    for (int a = 0; a < M; ++a) off[a] = G->off[a];
+    const int n = G->M2;
+    for_classes<UF, BS>(G, bases, pre, [&](const uint32_t (&base)[UF], const bool (&ok)[UF]) {
+        chain_classes<R, M, UF>(tile, U, n, off, base, ok);
+    });
+}
+
 // First gate at or after g whose outer controls hold for this tile (uniform).
 __device__ __forceinline__ int next_live_gate(const TileGate* __restrict__ gates, int g, int ngates, uint64_t obase) {
     for (; g < ngates; ++g) {
@@ -288,6 +337,14 @@ __device__ __forceinline__ void apply_gates(typename Cx<R>::T* tile, I obase, in
                 QD_PAIR_CASE(2, 2) QD_PAIR_CASE(2, 3) QD_PAIR_CASE(2, 4) QD_PAIR_CASE(3, 2) QD_PAIR_CASE(3, 3)
                 QD_PAIR_CASE(3, 4) QD_PAIR_CASE(4, 2) QD_PAIR_CASE(4, 3) QD_PAIR_CASE(4, 4)
 #undef QD_PAIR_CASE
+                default: break;
+            }
+        } else if (G->kind == kDenseChain) {
+            static_assert(kChainMaxM == 4, "a case per chain class size");
+            switch (G->M) {
+                case 2: tile_chain<R, 2, BS>(tile, G, U, bases, pre); break;
+                case 3: tile_chain<R, 3, BS>(tile, G, U, bases, pre); break;
+                case 4: tile_chain<R, 4, BS>(tile, G, U, bases, pre); break;
                 default: break;
             }
         } else if (G->kind == kDense) {
@@ -375,7 +432,7 @@ __device__ __forceinline__ void move_tile(T* __restrict__ psi, T* tile, I obase,
     }
 }
 
-// Threads per tile workgroup. Two 64 KB tiles share a CU; complex64 runs eight
+// Threads per tile workgroup. complex64 runs eight
 // wavefronts per tile (16 per CU), complex128 four: at eight its pass measured
 // slower (14.8 against 13.1 ms on the 1.72e9-amplitude register).
 template <typename R>

@@ -25,6 +25,17 @@ bool fusable(const GatePlan& p, int m) {
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Same targets in the same order, and the same controls with the same values:
+// the two gates act on the same classes with the same local member order.
+bool same_classes(const CircuitGate& a, const CircuitGate& b) {
+    if (a.k != b.k || a.m != b.m) return false;
+    for (int l = 0; l < a.k; ++l)
+        if (a.targets[l] != b.targets[l]) return false;
+    for (int l = 0; l < a.m; ++l)
+        if (a.controls[l] != b.controls[l] || a.values[l] != b.values[l]) return false;
+    return true;
+}
+
 template <typename R>
 void put_complex(unsigned char* dst, double re, double im) {
     R v[2] = {static_cast<R>(re), static_cast<R>(im)};
@@ -141,11 +152,28 @@ int build_fused(const int32_t* dims, int n, int precision, const CircuitGate* ga
         uint16_t* b = reinterpret_cast<uint16_t*>(udata.data() + t.bases_off);
         for (uint64_t c = 0; c < gp.n_classes; ++c) b[c] = (uint16_t)decode_base<uint64_t>(dec, c);
     };
+    // A chain continues while the next gate is dense on the same classes.
+    auto chains_with = [&](const Local& A, const Local& B) {
+        return A.plan.category == kDense && B.plan.category == kDense && A.plan.M <= kChainMaxM &&
+               same_classes(gates[A.gi], gates[B.gi]);
+    };
     GatePlan joint;  // geometry of a pair's joint class
     for (size_t i = 0; i < locs.size(); ++i) {
         Local& A = locs[i];
         TileGate t = A.t;
-        if (i + 1 < locs.size() && pairable(A, locs[i + 1])) {
+        size_t len = 1;
+        while (i + len < locs.size() && len < (size_t)kChainMaxLen && chains_with(A, locs[i + len])) ++len;
+        if (len > 1) {
+            const GatePlan& gpl = A.plan;
+            put_classes(t, gpl);
+            t.kind = kDenseChain;
+            t.M = gpl.M;
+            t.M2 = (int32_t)len;
+            for (int a = 0; a < gpl.M; ++a) t.off[a] = (uint32_t)gpl.off[a];
+            t.u_off = (uint32_t)udata.size();
+            for (size_t j = 0; j < len; ++j) put_u(gates[locs[i + j].gi].U, gpl.M);
+            i += len - 1;
+        } else if (i + 1 < locs.size() && pairable(A, locs[i + 1])) {
             // The joint class: targets of the first gate, then of the second (so the
             // joint local index is a1 + M1 a2); U = identity, only the geometry is used.
             const Local& B = locs[i + 1];
@@ -250,7 +278,7 @@ int plan_circuit(const int32_t* dims, int n, int precision, const CircuitGate* g
     // Every gate planned once: identity gates are dropped, the others noted with
     // their fusability, device-data bound and qudit masks.
     struct Info {
-        bool skip, can;
+        bool skip, can, chain;  // chain: dense with a class small enough for a chain
         size_t bytes;
         uint64_t tmask, cmask;
     };
@@ -264,6 +292,7 @@ int plan_circuit(const int32_t* dims, int n, int precision, const CircuitGate* g
             Info& f = info[i];
             f.skip = gp->category == kIdentity;
             f.can = opt.fuse && fusable(*gp, g.m);
+            f.chain = gp->category == kDense && gp->M <= kChainMaxM;
             f.bytes = sizeof(TileGate) + (size_t)tile_bound + (size_t)gp->M * gp->M * 16 + 64;
             f.tmask = f.cmask = 0;
             for (int l = 0; l < g.k; ++l) f.tmask |= 1ull << g.targets[l];
@@ -330,6 +359,28 @@ int plan_circuit(const int32_t* dims, int n, int precision, const CircuitGate* g
             if ((blockA & all) == all) break;
         }
         if (cur.empty()) continue;
+        if (opt.reorder > 0) {
+            // Within the pass, move each chain-sized dense gate back to the last
+            // gate on the same classes when it commutes with every gate in
+            // between, so that the two share a chain descriptor.
+            std::vector<int> seq;
+            seq.reserve(cur.size());
+            for (int gi : cur) {
+                const Info& f = info[gi];
+                size_t at = seq.size();
+                if (f.chain)
+                    for (size_t k = seq.size(); k-- > 0;) {
+                        const Info& h = info[seq[k]];
+                        if (h.chain && same_classes(gates[seq[k]], gates[gi])) {
+                            at = k + 1;
+                            break;
+                        }
+                        if ((f.tmask & (h.tmask | h.cmask)) || (f.cmask & h.tmask)) break;
+                    }
+                seq.insert(seq.begin() + (std::ptrdiff_t)at, gi);
+            }
+            cur.swap(seq);
+        }
         PassPlan pp;
         if (cur.size() == 1 && !opt.single_as_fused) {
             pp.fused = false;

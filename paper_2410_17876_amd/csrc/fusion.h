@@ -23,7 +23,7 @@ struct CircuitGate {
 
 struct CircuitOptions {
     bool fuse = true;
-    uint64_t tile_max = 4096;       // amplitudes per tile
+    uint64_t tile_max = 3072;       // amplitudes per tile
     uint64_t min_run = 64;          // minimum contiguous run inside a tile
     bool single_as_fused = false;   // run a one-gate pass as a tile pass too (batched rounds)
     int reorder = 0;                // look-ahead for commuting gates (0: strictly in order)

@@ -14,7 +14,7 @@ import time
 from typing import Callable, Dict, Iterable, Optional, Sequence, Tuple
 
 CANDIDATES = {
-    "c128": [(2048, 64), (4096, 64), (4096, 128), (8192, 128)],
+    "c128": [(2048, 64), (3072, 64), (4096, 64), (4096, 128), (8192, 128)],
     "c64": [(4096, 128), (8192, 128), (8192, 256), (16384, 256)],
 }
 

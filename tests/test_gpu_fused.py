@@ -103,6 +103,51 @@ def test_reordered_passes_equal_planned_order_and_oracle(precision, case):
     assert_close(a.amplitudes(), ref, precision, f"reordered {dims}")
 
 
+def chain_gates(rng, dims):
+    # runs of dense gates on the same targets (M = 2, 3, 4; a run longer than one
+    # chain descriptor holds; controls inside and outside the tile) with
+    # commuting gates on other qudits in between
+    out = []
+    runs = [((0,), (), ()), ((2,), (), ()), ((1,), (5,), (1,)), ((3,), (0,), (1,)), ((0, 4), (), ()),
+            ((7,), (), ())]
+    for targets, controls, values in runs:
+        M = math.prod(dims[t] for t in targets)
+        for j in range(int(rng.integers(3, 7)) if targets != (0,) else 20):
+            out.append(Gate(targets, haar(M, rng), controls, values))
+            if j % 3 == 2:  # a gate elsewhere: dense, monomial or diagonal, on qudits the run does not use
+                q = 6 if 6 not in targets else 8
+                out.append(Gate((q,), [haar(dims[q], rng), shift(dims[q]), clock(dims[q])][j % 3 - 2 + int(rng.integers(3))]))
+    return out
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_dense_chains_bitwise(precision):
+    dims = [2, 3, 3, 4, 2, 2, 3, 2, 5, 2, 3]
+    rng = np.random.default_rng(31)
+    psi0 = rand_state(rng, math.prod(dims))
+    gates = chain_gates(rng, dims)
+    tile = 2048 if precision == "c128" else 4096
+    # in order: adjacent same-target gates form chains
+    a = qd().State(dims, precision, init=None).set_amplitudes(psi0)
+    a.run_circuit(gates, tile_amps=tile, min_run=32)
+    c = qd().State(dims, precision, init=None).set_amplitudes(psi0)
+    c.run(gates)
+    assert np.array_equal(a.amplitudes(), c.amplitudes())
+    # look-ahead: the runs are gathered across the gates in between
+    passes, order = qd().circuit_plan(dims, gates, precision, tile_amps=tile, min_run=32, reorder=64, with_order=True)
+    b = qd().State(dims, precision, init=None).set_amplitudes(psi0)
+    b.run_circuit(gates, tile_amps=tile, min_run=32, reorder=64)
+    d = qd().State(dims, precision, init=None).set_amplitudes(psi0)
+    d.run([gates[i] for i in order])
+    assert np.array_equal(b.amplitudes(), d.amplitudes())
+    ref = psi0.copy() if precision == "c128" else (psi0.real.astype(np.float32).astype(np.float64) +
+                                                   1j * psi0.imag.astype(np.float32).astype(np.float64))
+    for g in gates:
+        oracle.apply_gate(dims, ref, g)
+    assert_close(a.amplitudes(), ref, precision, "chains in order")
+    assert_close(b.amplitudes(), ref, precision, "chains with look-ahead")
+
+
 @pytest.mark.parametrize("precision", ["c128", "c64"])
 def test_plain_circuit_in_one_launch(precision):
     dims, gates = circuits.plain()
