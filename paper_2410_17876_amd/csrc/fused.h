@@ -51,7 +51,7 @@ constexpr int kPairMaxM = 4;
 // it back once: bitwise the gate-by-gate result, with one LDS round trip and
 // one barrier for the whole chain.
 constexpr int32_t kDenseChain = 9;  // TileGate::kind of a chain; M2 = its length, the matrices follow each other
-constexpr int kChainMaxM = 4;
+constexpr int kChainMaxM = 3;  // at 4, one gate's matrix (64 scalar registers in complex128) spills
 constexpr int kChainMaxLen = 16;
 
 struct TileGate {

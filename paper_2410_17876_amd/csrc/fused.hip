@@ -340,11 +340,10 @@ __device__ __forceinline__ void apply_gates(typename Cx<R>::T* tile, I obase, in
                 default: break;
             }
         } else if (G->kind == kDenseChain) {
-            static_assert(kChainMaxM == 4, "a case per chain class size");
+            static_assert(kChainMaxM == 3, "a case per chain class size");
             switch (G->M) {
                 case 2: tile_chain<R, 2, BS>(tile, G, U, bases, pre); break;
                 case 3: tile_chain<R, 3, BS>(tile, G, U, bases, pre); break;
-                case 4: tile_chain<R, 4, BS>(tile, G, U, bases, pre); break;
                 default: break;
             }
         } else if (G->kind == kDense) {
