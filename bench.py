@@ -48,6 +48,8 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBPS = 8000.0
 PEAK_MFMA_TFLOPS = {"c64": 157.3, "c128": 78.6}  # dense FP32 / FP64 matrix peaks
+# vector FMA peaks: 256 CUs x 2.4 GHz x 256 (FP32) or 128 (FP64) flops per clock per CU
+PEAK_VALU_TFLOPS = {"c64": 157.3, "c128": 78.6}
 
 
 def log(msg: str) -> None:
@@ -180,9 +182,15 @@ def run_mode(qd, st, dims, gates, precision, mode, steps, warmup):
                 "bytes_per_launch": d["bytes"] // d["launches"]}
     else:
         achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
+        alu = d["flops"] / (d["ms"] * 1e-3) / 1e12
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": load_traffic(dom), "kernel": dom,
-                "avg_us": kernels[dom]["avg_us"], "bytes_per_launch": d["bytes"] // d["launches"]}
+                "avg_us": kernels[dom]["avg_us"], "bytes_per_launch": d["bytes"] // d["launches"],
+                # the same launches against the vector ALU: the gates' useful flops (8 M per
+                # changed amplitude, dense gates) per second over the FP64 / FP32 vector peak
+                "alu_tflops": round(alu, 2), "alu_peak_tflops": PEAK_VALU_TFLOPS[precision],
+                "alu_frac": round(alu / PEAK_VALU_TFLOPS[precision], 4),
+                "flops_per_launch": d["flops"] // d["launches"]}
     return {
         "value": updates / wall,
         "ms_per_step": 1e3 * wall / steps,
@@ -289,13 +297,14 @@ def run_batched(qd, precision, steps, warmup, tune_cache, lookahead):
                          "note": "whole-run average over all rounds: 2 x D x bytes per (state, pass)"}}
 
 
-def run_served(qd, n_closed, n_open, loads):
+def run_served(qd, n_closed, n_open, loads, lookahead):
     """The served workload: requests with log-uniform sizes in [1e3, 1e8]
     amplitudes (d in 2..7), depth 50..500 of the basic mix, complex64, admitted
     under a 200 GB HBM budget. First the closed-loop capacity (all requests
     present at t = 0), then open-loop Poisson arrivals at each of `loads` x
     capacity. One request stream is generated (at rate 1/s) and reused: Poisson
-    arrivals at rate q are the rate-1 arrival times divided by q."""
+    arrivals at rate q are the rate-1 arrival times divided by q. Every tick's
+    passes use the given commuting look-ahead."""
     import torch
     from qd_inputs import circuits
 
@@ -311,11 +320,11 @@ def run_served(qd, n_closed, n_open, loads):
 
     upd = lambda reqs: sum(qd.gate_info(r.dims, g.targets, g.U, g.controls, g.values, "c64")["updated"]
                            for r in reqs for g in r.gates.gates)
-    srv = qd.serve.Server("c64", budget_bytes=200e9, quantum=32)
+    srv = qd.serve.Server("c64", budget_bytes=200e9, quantum=32, reorder=lookahead)
     srv.run(fresh(16, 0), realtime=False)  # warm-up
     srv.close()
     closed = fresh(n_closed, 0)
-    srv = qd.serve.Server("c64", budget_bytes=200e9, quantum=32)
+    srv = qd.serve.Server("c64", budget_bytes=200e9, quantum=32, reorder=lookahead)
     rc = srv.run(closed, realtime=False)
     srv.close()
     cap = rc["throughput_rps"]
@@ -323,7 +332,7 @@ def run_served(qd, n_closed, n_open, loads):
     opened = {}
     for load in loads:
         reqs = fresh(n_open, load * cap)
-        srv = qd.serve.Server("c64", budget_bytes=200e9, quantum=32)
+        srv = qd.serve.Server("c64", budget_bytes=200e9, quantum=32, reorder=lookahead)
         ro = srv.run(reqs, realtime=True)
         srv.close()
         ro = dict(ro, offered_rps=load * cap, load=load, updates_per_s=upd(reqs) / ro["wall_s"])
@@ -338,7 +347,8 @@ def run_served(qd, n_closed, n_open, loads):
                             "updates_per_s": upd(closed) / rc["wall_s"], "p50_ms": rc["p50_ms"],
                             "p99_ms": rc["p99_ms"]},
             "open_loop": opened,
-            "latency": "arrival -> final state resident and its FP64 norm returned to the host"}
+            "latency": "arrival -> final state resident and its FP64 norm returned to the host",
+            "lookahead": lookahead}
 
 
 def cpu_baseline(qd, dims, gates, psi, seconds):
@@ -439,7 +449,7 @@ def main() -> int:
             res[f"batched_{p}"] = run_batched(qd, p, args.steps, args.warmup, args.tune_cache, args.lookahead)
     if not args.no_served:
         res["served"] = run_served(qd, args.served_closed, args.served_open,
-                                   [float(x) for x in args.served_loads.split(",")])
+                                   [float(x) for x in args.served_loads.split(",")], args.lookahead)
     cpu = None
     if host is not None:
         cpu = cpu_baseline(qd, dims, gates, host, args.cpu_seconds)

@@ -14,7 +14,11 @@ one HIP event per tick.
 Per-request arithmetic does not depend on the mix: a fused pass applies each of
 its gates with the same per-class arithmetic as a lone gate, so a request's
 final state is bitwise the same whether it ran alone or among others, and
-however its circuit was cut into quanta.
+however its circuit was cut into quanta. With `reorder` > 0 each tick's passes
+also take later gates of the quantum that commute with the gates they skip
+(qd_circuit_options.reorder): fewer passes per tick, and a final state equal to
+the in-order one up to rounding (the planned order depends on the quantum
+boundaries, so bitwise equality with a solo run no longer holds).
 """
 from __future__ import annotations
 
@@ -55,7 +59,7 @@ class ServeRequest:
 class Server:
     def __init__(self, precision: str = "c64", budget_bytes: float = 200e9, max_slots: int = 256,
                  quantum: int = 32, tile_amps: int = 0, min_run: int = 0, keep_states: bool = False,
-                 tick_updates: float = 5e8):
+                 tick_updates: float = 5e8, reorder: int = 0):
         import torch
 
         self.torch = torch
@@ -69,7 +73,7 @@ class Server:
         # quantum ticks, each as long as the largest resident request's quantum.
         self.quantum = quantum
         self.tick_updates = tick_updates
-        self.tile_amps, self.min_run = tile_amps, min_run
+        self.tile_amps, self.min_run, self.reorder = tile_amps, min_run, reorder
         self.keep_states = keep_states
         self.batch = Batch(precision)
         self.stream = torch.cuda.current_stream()
@@ -134,7 +138,8 @@ class Server:
             q = max(self.quantum, int(self.tick_updates // r.D))
             lists.append(r.gates.view(r.pos, q))  # no re-marshalling per tick
             r.pos += len(lists[-1])
-        self.batch.apply([r.state for r in work], lists, tile_amps=self.tile_amps, min_run=self.min_run)
+        self.batch.apply([r.state for r in work], lists, tile_amps=self.tile_amps, min_run=self.min_run,
+                         reorder=self.reorder)
         ev = self.torch.cuda.Event()
         ev.record(self.stream)
         self.events[self.ticks] = ev

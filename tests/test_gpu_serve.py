@@ -43,6 +43,20 @@ def test_served_results_equal_alone_and_oracle(precision):
     srv.close()
 
 
+@pytest.mark.parametrize("precision", ["c64", "c128"])
+def test_served_with_lookahead_matches_oracle(precision):
+    # ticks planned with a commuting look-ahead: the order within each quantum
+    # changes, the state agrees with the in-order one up to rounding
+    specs, reqs = make_requests(24, qps=400.0, lo=1e3, hi=2e4, depth_lo=40, depth_hi=160, seed=33)
+    srv = qd().serve.Server(precision, budget_bytes=50e9, quantum=16, keep_states=True, reorder=64)
+    rep = srv.run(reqs, realtime=True)
+    assert rep["requests"] == 24 and rep["rejected"] == 0
+    for r, sp in zip(sorted(srv.finished, key=lambda r: r.rid), specs):
+        assert abs(r.norm - 1.0) < (1e-12 if precision == "c128" else 1e-4)
+        assert_close(r.state.amplitudes(), oracle.run(sp.spec.dims, sp.spec.gates()), precision, f"request {r.rid}")
+    srv.close()
+
+
 def test_budget_is_respected_and_oversized_rejected():
     specs, reqs = make_requests(30, qps=1000.0, lo=1e4, hi=1e6, depth_lo=10, depth_hi=40, seed=32)
     biggest = max(r.D for r in reqs) * 8
