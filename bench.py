@@ -87,6 +87,7 @@ def load_traffic(kernel: str):
 
 
 TILE = {"c128": 0, "c64": 0}
+MIN_RUN = {"c128": 0, "c64": 0}
 # Look-ahead of the planner in "lookahead" mode: a pass also takes later gates
 # that commute with the ones it skips (qd_circuit_options.reorder).
 LOOKAHEAD = 128
@@ -105,7 +106,8 @@ def build_units(qd, dims, gates, precision, mode):
             units.append((kernel_key(info, precision), info["bytes"], info["updated"], ("gate", g), info["flops"]))
         return units
     reorder = LOOKAHEAD if mode == "lookahead" else 0  # LOOKAHEAD: set from --lookahead
-    plan, order = qd.circuit_plan(dims, gates, precision, tile_amps=TILE[precision], reorder=reorder,
+    plan, order = qd.circuit_plan(dims, gates, precision, tile_amps=TILE[precision], min_run=MIN_RUN[precision],
+                                  reorder=reorder,
                                   with_order=True)
     live = [i for i, info in enumerate(infos) if info["kernel"] != "identity"]
     assert sorted(order) == live
@@ -139,7 +141,7 @@ def run_mode(qd, st, dims, gates, precision, mode, steps, warmup):
             if kind == "gate":
                 st.apply_gate(obj)
             else:
-                st.run_circuit(obj, fuse=True, tile_amps=TILE[precision])
+                st.run_circuit(obj, fuse=True, tile_amps=TILE[precision], min_run=MIN_RUN[precision])
             if events is not None:
                 events[u][1].record(stream)
         return st.norm()
@@ -395,6 +397,10 @@ def main() -> int:
     ap.add_argument("--small", action="store_true", help="2^10 x 3^6 x 4^2 register (quick check)")
     ap.add_argument("--tile-c128", type=int, default=0, help="fused tile size, c128 (0 = library default)")
     ap.add_argument("--tile-c64", type=int, default=0, help="fused tile size, c64 (0 = library default)")
+    ap.add_argument("--min-run-c128", type=int, default=0,
+                    help="contiguous run a fused tile must hold, c128 (0 = library default)")
+    ap.add_argument("--min-run-c64", type=int, default=0,
+                    help="contiguous run a fused tile must hold, c64 (0 = library default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported (the sharded multi-GPU "
@@ -416,6 +422,7 @@ def main() -> int:
     G = states.GaussianState(D, seed=circuits.SEEDS["large"])
     modes = [m for m in args.modes.split(",") if m]
     TILE["c128"], TILE["c64"] = args.tile_c128, args.tile_c64
+    MIN_RUN["c128"], MIN_RUN["c64"] = args.min_run_c128, args.min_run_c64
     LOOKAHEAD = args.lookahead
     t0 = time.time()
     host = None

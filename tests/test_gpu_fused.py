@@ -120,6 +120,51 @@ def chain_gates(rng, dims):
     return out
 
 
+def group_gates(rng, dims, count):
+    # mostly uncontrolled 1-qudit gates of every category on qubits and qutrits
+    # (group candidates), broken up by controlled and 2-qudit gates
+    n, out = len(dims), []
+    small = [q for q in range(n) if dims[q] <= 3]
+    while len(out) < count:
+        r = rng.random()
+        if r < 0.8:
+            q = int(rng.choice(small))
+            d = dims[q]
+            kind = int(rng.integers(6))
+            U = [haar(d, rng), dft(d), shift(d, int(rng.integers(1, d)) if d > 1 else 0), clock(d),
+                 rand_monomial(rng, d), np.diag(np.where(rng.random(d) < 0.5, 1.0, np.exp(2j * np.pi * rng.random(d))))][kind]
+            out.append(Gate((q,), U))
+        elif r < 0.9:
+            c, t = (int(x) for x in rng.choice(n, 2, replace=False))
+            out.append(Gate((t,), haar(dims[t], rng), (c,), (int(rng.integers(dims[c])),)))
+        else:
+            a, b = (int(x) for x in rng.choice(small, 2, replace=False))
+            out.append(Gate((a, b), haar(dims[a] * dims[b], rng)))
+    return out
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+@pytest.mark.parametrize("reorder", [0, 64])
+def test_groups_bitwise(precision, reorder):
+    dims = [2, 3, 2, 2, 3, 4, 2, 3, 2, 5, 2]
+    rng = np.random.default_rng(41 + reorder)
+    psi0 = rand_state(rng, math.prod(dims))
+    gates = group_gates(rng, dims, 150)
+    tile = 2048 if precision == "c128" else 4096
+    passes, order = qd().circuit_plan(dims, gates, precision, tile_amps=tile, min_run=16, reorder=reorder,
+                                      with_order=True)
+    a = qd().State(dims, precision, init=None).set_amplitudes(psi0)
+    a.run_circuit(gates, tile_amps=tile, min_run=16, reorder=reorder)
+    c = qd().State(dims, precision, init=None).set_amplitudes(psi0)
+    c.run([gates[i] for i in order])
+    assert np.array_equal(a.amplitudes(), c.amplitudes())
+    ref = psi0.copy() if precision == "c128" else (psi0.real.astype(np.float32).astype(np.float64) +
+                                                   1j * psi0.imag.astype(np.float32).astype(np.float64))
+    for g in gates:
+        oracle.apply_gate(dims, ref, g)
+    assert_close(a.amplitudes(), ref, precision, f"groups, reorder {reorder}")
+
+
 @pytest.mark.parametrize("precision", ["c128", "c64"])
 def test_dense_chains_bitwise(precision):
     dims = [2, 3, 3, 4, 2, 2, 3, 2, 5, 2, 3]
