@@ -30,7 +30,10 @@ launch (profiles/*traffic*.json, when taken for the current kernel source).
 
 Also reported: the in-place read+rewrite copy ceiling measured on the same
 buffer (qd_copy_ceiling), and the FP64 oracle (one thread) on the first gates
-of the same circuit and state as the CPU baseline.
+of the same circuit and state as the CPU baseline. Further runs under `runs`:
+the 12-ququint workload (300 Haar gates of 25 and 125 members, MFMA) in
+complex64 and complex128, the 512-circuit batched workload and the served
+workload.
 """
 from __future__ import annotations
 
@@ -383,7 +386,7 @@ def main() -> int:
                     help="look-ahead in gates for lookahead mode and the batched runs (0 = in order)")
     ap.add_argument("--no-c64", action="store_true", help="skip the complex64 runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-ququint", action="store_true", help="skip the 12-ququint MFMA workload")
+    ap.add_argument("--no-ququint", action="store_true", help="skip the 12-ququint MFMA workloads")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-circuit batched workload")
     ap.add_argument("--no-served", action="store_true", help="skip the served (continuous batching) workload")
     ap.add_argument("--served-closed", type=int, default=600,
@@ -451,6 +454,11 @@ def main() -> int:
         qst.close()
         del qst
         torch.cuda.empty_cache()
+        qst = qd.State(qdims, "c128")
+        res["ququint_c128"] = run_mode(qd, qst, qdims, qgates, "c128", "plain", args.steps, args.warmup)
+        qst.close()
+        del qst
+        torch.cuda.empty_cache()
     if not args.no_batched:
         for p in (["c64", "c128"] if not args.no_c64 else ["c128"]):
             res[f"batched_{p}"] = run_batched(qd, p, args.steps, args.warmup, args.tune_cache, args.lookahead)
@@ -495,6 +503,13 @@ def main() -> int:
         line["runs"]["ququint_mfma_c64"] = {
             "workload": "12 ququints (D=5^12), complex64, 300 Haar gates on 2 or 3 qudits (seed 1004), |0..0>",
             "value": r["value"], "unit": "updates/s", "dtype": "f32", "ms_per_step": r["ms_per_step"],
+            "launches_per_step": r["launches_per_step"], "roofline": r["roofline"],
+            "norm_last_step": r["norm_last_step"], "kernels": r["kernels"]}
+    if "ququint_c128" in res:
+        r = res["ququint_c128"]
+        line["runs"]["ququint_mfma_c128"] = {
+            "workload": "12 ququints (D=5^12), complex128, the same 300 Haar gates (seed 1004), |0..0>",
+            "value": r["value"], "unit": "updates/s", "dtype": "f64", "ms_per_step": r["ms_per_step"],
             "launches_per_step": r["launches_per_step"], "roofline": r["roofline"],
             "norm_last_step": r["norm_last_step"], "kernels": r["kernels"]}
     if "served" in res:

@@ -18,7 +18,7 @@ int plan_family(const GatePlan& p, int precision);
 const char* family_name(int family);
 
 // Matrix-core path (mfma.hip): dense gates with 17 <= M <= mfma_max_m(precision)
-// (128 for complex64 on FP32 MFMA, 64 for complex128 on FP64 MFMA).
+// (128: complex64 on FP32 MFMA, complex128 on FP64 MFMA).
 constexpr int kMfmaMinM = 17;
 int mfma_max_m(int precision);
 int mfma_padded(int M);

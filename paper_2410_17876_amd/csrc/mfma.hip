@@ -1,5 +1,5 @@
-// mfma.hip - dense class updates on the matrix cores (complex64 with
-// 17 <= M <= 128 on FP32 MFMA, complex128 with 17 <= M <= 64 on FP64 MFMA).
+// mfma.hip - dense class updates on the matrix cores (17 <= M <= 128:
+// complex64 on FP32 MFMA, complex128 on FP64 MFMA).
 //
 // For a gate with a large class (several target qudits, e.g. a 25x25 or 125x125
 // block on ququints) the per-class update y = U x (paper Sec. 2.3) is a dense
@@ -11,10 +11,11 @@
 //
 // a real (2MP x 2MP) by (2MP x N) product with MP = M rounded up to 32, 64 or
 // 128 (padding rows and columns of the real matrix are zero). A workgroup has
-// eight wavefronts; each owns one row block of the real matrix (32 rows for
+// eight wavefronts; each owns row blocks of the real matrix (32 rows for
 // v_mfma_f32_32x32x2f32, 16 for v_mfma_f64_16x16x4f64), kept in registers for
-// the whole launch (persistent workgroups loop over column tiles), and one or
-// more column blocks of the tile. Per column tile the workgroup gathers the
+// the whole launch (persistent workgroups loop over column tiles) except for
+// the 256 x 256 FP64 form, which is streamed from L2, and one or more column
+// blocks of the tile. Per column tile the workgroup gathers the
 // classes' amplitudes into LDS (split into real and imaginary rows), runs the
 // MFMAs over K = 2MP, writes the result blocks back to LDS and scatters them to
 // the classes' addresses. A tile's classes are read completely before any of
@@ -51,22 +52,29 @@ struct MfmaShape;
 // real matrix and one 32-column block of the tile; K advances 2 per step.
 template <int MP>
 struct MfmaShape<float, MP> {
+    static constexpr bool STREAM = false;
     static constexpr int RB = 2 * MP / 32;  // row blocks
     static constexpr int NT = 32 * (8 / RB);
     static constexpr int KS = MP;            // K steps
 };
 
-// complex128, v_mfma_f64_16x16x4f64: a wavefront owns one 16-row block and CB
-// 16-column blocks (CB independent accumulators); K advances 4 per step. The
-// real matrix must fit the eight wavefronts' registers: MP <= 64. Both sizes
-// tile 64 classes (MP = 32 with two column groups of two blocks, which keeps
-// the kernel within 128 VGPRs: two workgroups per CU).
+// complex128, v_mfma_f64_16x16x4f64: a wavefront owns RW 16-row blocks and CB
+// 16-column blocks (RW x CB independent accumulators); K advances 4 per step.
+// Up to MP = 64 the real matrix sits in the eight wavefronts' registers for
+// the whole launch (both sizes tile 64 classes; MP = 32 with two column groups
+// of two blocks keeps the kernel within 128 VGPRs: two workgroups per CU). At
+// MP = 128 (256 x 256 doubles, 512 KB) it stays in L2 and is streamed: the
+// host stores it in fragment order, so a wavefront's fragment for one K step is
+// 512 contiguous bytes, and each wavefront owns two row blocks over a
+// 32-class tile (67 KB of LDS: two workgroups per CU).
 template <int MP>
 struct MfmaShape<double, MP> {
-    static_assert(MP <= 64, "complex128 matrix-core blocks hold at most 64 members");
+    static_assert(MP <= 128, "complex128 matrix-core blocks hold at most 128 members");
+    static constexpr bool STREAM = MP == 128;
     static constexpr int RB = 2 * MP / 16;
-    static constexpr int CB = MP == 32 ? 2 : 4;
-    static constexpr int NT = 16 * CB * (8 / RB);
+    static constexpr int RW = STREAM ? 2 : 1;  // row blocks per wavefront
+    static constexpr int CB = MP == 32 ? 2 : (STREAM ? 2 : 4);
+    static constexpr int NT = STREAM ? 16 * CB : 16 * CB * (8 / RB);
     static constexpr int KS = MP / 2;
 };
 
@@ -110,13 +118,15 @@ __global__ __launch_bounds__(kMfmaBlock) void block_mfma(typename Cx<R>::T* __re
     // This wavefront's rows of the real matrix, all of K = 2MP, as MFMA A
     // fragments: f32 32x32x2 lane l holds row l mod 32, K column 2s + l / 32;
     // f64 16x16x4 lane l holds row l mod 16, K column 4s + l / 16.
-    R a[S::KS];
+    R a[S::STREAM ? 1 : S::KS];
+    if constexpr (!S::STREAM) {
 #pragma unroll
-    for (int s = 0; s < S::KS; ++s) {
-        if constexpr (kF32)
-            a[s] = A[(size_t)(32 * rb + (lane & 31)) * K2 + 2 * s + (lane >> 5)];
-        else
-            a[s] = A[(size_t)(16 * rb + (lane & 15)) * K2 + 4 * s + (lane >> 4)];
+        for (int s = 0; s < S::KS; ++s) {
+            if constexpr (kF32)
+                a[s] = A[(size_t)(32 * rb + (lane & 31)) * K2 + 2 * s + (lane >> 5)];
+            else
+                a[s] = A[(size_t)(16 * rb + (lane & 15)) * K2 + 4 * s + (lane >> 4)];
+        }
     }
     for (int i = threadIdx.x; i < MP; i += kMfmaBlock) {
         offs[i] = i < M ? off[i] : (I)0;
@@ -219,6 +229,43 @@ __global__ __launch_bounds__(kMfmaBlock) void block_mfma(typename Cx<R>::T* __re
 #pragma unroll
             for (int r = 0; r < 16; ++r)
                 Bs[32 * rb + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)][32 * cb + (lane & 31)] = acc[r];
+        } else if constexpr (S::STREAM) {
+            // Wavefront w: row blocks w and w + 8, all CB column blocks. A's
+            // fragment for (row block r, step s) is A[(r * KS + s) * 64 + lane].
+            constexpr int CB = S::CB;
+            f64x4 acc[2][CB];
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int c = 0; c < CB; ++c) acc[h][c] = f64x4{0.0, 0.0, 0.0, 0.0};
+            const R* __restrict__ A0 = A + (size_t)wave * S::KS * 64 + lane;
+            const R* __restrict__ A1 = A + (size_t)(wave + 8) * S::KS * 64 + lane;
+#pragma unroll 4
+            for (int s0 = 0; s0 < S::KS; s0 += 4) {
+                double a0[4], a1[4], b[4][CB];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    a0[j] = A0[(s0 + j) * 64];
+                    a1[j] = A1[(s0 + j) * 64];
+#pragma unroll
+                    for (int c = 0; c < CB; ++c) b[j][c] = Bs[4 * (s0 + j) + (lane >> 4)][16 * c + (lane & 15)];
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+#pragma unroll
+                    for (int c = 0; c < CB; ++c) {
+                        acc[0][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[j], b[j][c], acc[0][c], 0, 0, 0);
+                        acc[1][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[j], b[j][c], acc[1][c], 0, 0, 0);
+                    }
+            }
+            __syncthreads();  // every wavefront has read its B fragments
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int c = 0; c < CB; ++c)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        Bs[16 * (wave + 8 * h) + 4 * r + (lane >> 4)][16 * c + (lane & 15)] = acc[h][c][r];
         } else {
             constexpr int CB = S::CB;
             f64x4 acc[CB];
@@ -264,7 +311,7 @@ __global__ __launch_bounds__(kMfmaBlock) void block_mfma(typename Cx<R>::T* __re
 
 int mfma_padded(int M) { return M <= 32 ? 32 : (M <= 64 ? 64 : 128); }
 
-int mfma_max_m(int precision) { return precision == kC128 ? 64 : 128; }
+int mfma_max_m(int /*precision*/) { return 128; }  // both precisions: FP32 and FP64 MFMA up to 128
 
 static size_t mfma_real_bytes(int precision) { return precision == kC128 ? sizeof(double) : sizeof(float); }
 
@@ -313,7 +360,8 @@ static void mfma_rmap(const GatePlan& p, const Order& o, int32_t* rmap) {
 
 static int mfma_nt(int M, int precision) {
     const int MP = mfma_padded(M);
-    if (precision == kC128) return MP == 32 ? MfmaShape<double, 32>::NT : MfmaShape<double, 64>::NT;
+    if (precision == kC128)
+        return MP == 32 ? MfmaShape<double, 32>::NT : (MP == 64 ? MfmaShape<double, 64>::NT : MfmaShape<double, 128>::NT);
     return MP == 32 ? MfmaShape<float, 32>::NT : (MP == 64 ? MfmaShape<float, 64>::NT : MfmaShape<float, 128>::NT);
 }
 
@@ -336,10 +384,22 @@ static void fill_real(const GatePlan& p, const double* U, R* A) {
 
 void fill_mfma_gate(const GatePlan& p, int precision, const double* U, void* dst) {
     const int K2 = 2 * mfma_padded(p.M);
-    if (precision == kC128)
+    if (precision == kC128 && MfmaShape<double, 128>::STREAM && mfma_padded(p.M) == 128) {
+        // Fragment order for the streamed kernel: entry (r * KS + s) * 64 + l is
+        // the real form's row 16 r + l mod 16, column 4 s + l / 16.
+        using S = MfmaShape<double, 128>;
+        std::vector<double> rm((size_t)K2 * K2);
+        fill_real<double>(p, U, rm.data());
+        double* A = static_cast<double*>(dst);
+        for (int r = 0; r < S::RB; ++r)
+            for (int st = 0; st < S::KS; ++st)
+                for (int l = 0; l < 64; ++l)
+                    A[((size_t)r * S::KS + st) * 64 + l] = rm[(size_t)(16 * r + l % 16) * K2 + 4 * st + l / 16];
+    } else if (precision == kC128) {
         fill_real<double>(p, U, static_cast<double*>(dst));
-    else
+    } else {
         fill_real<float>(p, U, static_cast<float*>(dst));
+    }
     unsigned char* o = static_cast<unsigned char*>(dst) + (size_t)K2 * K2 * mfma_real_bytes(precision);
     const bool narrow = p.D < (1ull << 31);
     if (narrow) {
@@ -395,7 +455,7 @@ static hipError_t launch_mfma_typed(const GatePlan& p, int precision, void* psi,
     if (precision == kC128) {
         if (MP == 32) return run_mfma<double, 32, I>(p, psi, dgate, st);
         if (MP == 64) return run_mfma<double, 64, I>(p, psi, dgate, st);
-        return hipErrorInvalidValue;  // the planner sends complex128 blocks above 64 members to the LDS sweep
+        return run_mfma<double, 128, I>(p, psi, dgate, st);
     }
     if (MP == 32) return run_mfma<float, 32, I>(p, psi, dgate, st);
     if (MP == 64) return run_mfma<float, 64, I>(p, psi, dgate, st);

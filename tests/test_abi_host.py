@@ -101,14 +101,15 @@ def test_gate_categories_from_zero_pattern():
     assert cx["category"] == 1 and cx["classes"] == 3 and cx["updated"] == 6 and cx["bytes"] == 2 * 6 * 8
     h = qd.gate_info(dims, [0, 2], haar(10, rng))
     assert h["kernel"] == "sweep_dense_reg" and h["flops"] == 8 * 30 * 10
-    assert qd.gate_info([5, 5, 5, 2], [0, 1, 2], haar(125, rng))["kernel"] == "sweep_dense_lds"
+    assert qd.gate_info([5, 5, 5, 2], [0, 1, 2], haar(125, rng))["kernel"] == "block_mfma"
     assert qd.gate_info([5, 5, 5, 2], [0, 1, 2], haar(125, rng), precision="c64")["kernel"] == "block_mfma"
     assert qd.gate_info([5, 5, 2], [0, 1], haar(25, rng), precision="c64")["kernel"] == "block_mfma"
     assert qd.gate_info([7, 7, 7], [0, 1, 2], haar(343, rng), precision="c64")["kernel"] == "sweep_dense_lds"
-    # complex128 takes the FP64 matrix cores up to M = 64 (the real matrix fits the registers)
+    # complex128 takes the FP64 matrix cores up to M = 128 (above 64 with the matrix streamed from L2)
     assert qd.gate_info([5, 5, 2], [0, 1], haar(25, rng), precision="c128")["kernel"] == "block_mfma"
     assert qd.gate_info([4, 4, 4, 2], [0, 1, 2], haar(64, rng), precision="c128")["kernel"] == "block_mfma"
-    assert qd.gate_info([6, 6, 2, 3], [0, 1, 2], haar(72, rng), precision="c128")["kernel"] == "sweep_dense_lds"
+    assert qd.gate_info([6, 6, 2, 3], [0, 1, 2], haar(72, rng), precision="c128")["kernel"] == "block_mfma"
+    assert qd.gate_info([7, 7, 7], [0, 1, 2], haar(343, rng), precision="c128")["kernel"] == "sweep_dense_lds"
     assert qd.gate_info([4, 4, 2], [0, 1], haar(16, rng), precision="c128")["kernel"] == "sweep_dense_reg"
 
 

@@ -1,6 +1,7 @@
-"""Matrix-core path (dense gates with 17 <= M <= 128 in complex64 on FP32 MFMA,
-17 <= M <= 64 in complex128 on FP64 MFMA) against the FP64 oracle, and the
-ququint workload: 2- and 3-qudit Haar gates (25x25, 125x125).
+"""Matrix-core path (dense gates with 17 <= M <= 128: complex64 on FP32 MFMA,
+complex128 on FP64 MFMA, its 256 x 256 real form streamed from L2 above 64
+members) against the FP64 oracle, and the ququint workload: 2- and 3-qudit
+Haar gates (25x25, 125x125).
 
 Tolerance: complex64, max-abs <= 2e-5 and <= 1e-5 of the largest amplitude,
 per gate layer (a layer = one gate, as each gate is one launch here);
@@ -49,7 +50,7 @@ def _m(dims, targets):
     return math.prod(dims[t] for t in targets)
 
 
-PCASES = [(d, t, "c64") for d, t in CASES] + [(d, t, "c128") for d, t in CASES if _m(d, t) <= 64]
+PCASES = [(d, t, "c64") for d, t in CASES] + [(d, t, "c128") for d, t in CASES]
 
 
 @pytest.mark.parametrize("dims,targets,precision", PCASES)
@@ -70,13 +71,15 @@ def test_mfma_gate_vs_oracle(dims, targets, precision):
 
 
 def test_mfma_c128_roundtrip_and_determinism():
-    # FP64 matrix cores: 64x64 (three ququarts) and 25x25 (two ququints) blocks,
+    # FP64 matrix cores: 64x64 (three ququarts), 25x25 (two ququints) and, streamed,
+    # 75x75 and 100x100 blocks,
     # with ragged last tiles (D / M classes is no multiple of the tile width)
     rng = np.random.default_rng(9)
     dims = [4, 5, 4, 5, 4, 3, 2]
     psi0 = rand_state(rng, math.prod(dims))
     gates = [Gate((4, 0, 2), haar(64, rng)), Gate((1, 3), haar(25, rng)), Gate((3, 1), haar(25, rng)),
-             Gate((2, 4, 0), haar(64, rng)), Gate((0, 2, 4), haar(64, rng), (5,), (2,))]
+             Gate((2, 4, 0), haar(64, rng)), Gate((0, 2, 4), haar(64, rng), (5,), (2,)),
+             Gate((1, 3, 5), haar(75, rng)), Gate((3, 2, 1), haar(100, rng), (6,), (1,))]
     for g in gates:
         assert qd().gate_info(dims, g.targets, g.U, precision="c128")["kernel"] == "block_mfma"
     a = qd().State(dims, "c128", init=None).set_amplitudes(psi0).run(gates)
@@ -152,7 +155,7 @@ def test_64bit_path_mfma_c128():
     upload_chunks(st, lambda s, c: states.labelled(s, c), chunk=1 << 24)
     rng = np.random.default_rng(12)
     idx = np.concatenate([rng.integers(0, D, size=3000), [0, D - 1]])
-    for targets in ((12, 3), (0, 13, 6)):
+    for targets in ((12, 3), (0, 13, 6), (12, 3, 7)):
         M = math.prod(dims[t] for t in targets)
         g = Gate(targets, haar(M, rng))
         assert qd().gate_info(dims, targets, g.U, precision="c128")["kernel"] == "block_mfma"
