@@ -238,20 +238,21 @@ __global__ __launch_bounds__(kMfmaBlock) void block_mfma(typename Cx<R>::T* __re
             for (int h = 0; h < 2; ++h)
 #pragma unroll
                 for (int c = 0; c < CB; ++c) acc[h][c] = f64x4{0.0, 0.0, 0.0, 0.0};
+            constexpr int KG = 2;  // K steps per group: at 4 the kernel needs 140 VGPRs (one workgroup per CU)
             const R* __restrict__ A0 = A + (size_t)wave * S::KS * 64 + lane;
             const R* __restrict__ A1 = A + (size_t)(wave + 8) * S::KS * 64 + lane;
 #pragma unroll 4
-            for (int s0 = 0; s0 < S::KS; s0 += 4) {
-                double a0[4], a1[4], b[4][CB];
+            for (int s0 = 0; s0 < S::KS; s0 += KG) {
+                double a0[KG], a1[KG], b[KG][CB];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
+                for (int j = 0; j < KG; ++j) {
                     a0[j] = A0[(s0 + j) * 64];
                     a1[j] = A1[(s0 + j) * 64];
 #pragma unroll
                     for (int c = 0; c < CB; ++c) b[j][c] = Bs[4 * (s0 + j) + (lane >> 4)][16 * c + (lane & 15)];
                 }
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
+                for (int j = 0; j < KG; ++j)
 #pragma unroll
                     for (int c = 0; c < CB; ++c) {
                         acc[0][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[j], b[j][c], acc[0][c], 0, 0, 0);
