@@ -60,20 +60,22 @@ struct MfmaShape<float, MP> {
 
 // complex128, v_mfma_f64_16x16x4f64: a wavefront owns RW 16-row blocks and CB
 // 16-column blocks (RW x CB independent accumulators); K advances 4 per step.
-// Up to MP = 64 the real matrix sits in the eight wavefronts' registers for
-// the whole launch (both sizes tile 64 classes; MP = 32 with two column groups
-// of two blocks keeps the kernel within 128 VGPRs: two workgroups per CU). At
-// MP = 128 (256 x 256 doubles, 512 KB) it stays in L2 and is streamed: the
-// host stores it in fragment order, so a wavefront's fragment for one K step is
-// 512 contiguous bytes, and each wavefront owns two row blocks over a
-// 32-class tile (67 KB of LDS: two workgroups per CU).
+// Up to MP = 64 the real matrix sits in the eight wavefronts' registers for the
+// whole launch (both sizes tile 64 classes; MP = 32 with two column groups of
+// two blocks keeps the kernel within 128 VGPRs: two workgroups per CU). At
+// MP = 128 (256 x 256 doubles, 512 KB) it stays in L2 and is streamed: the host
+// stores it in fragment order, so a wavefront's fragment for one K step is 512
+// contiguous bytes, and wavefront w owns row blocks w and w + 8 over a
+// 32-class tile (67 KB of LDS, 126 VGPRs: two workgroups per CU). Streamed at
+// MP = 64 as well, the 64-member gate measured 3.0 ms against 2.8 ms from
+// registers on 14 ququarts.
 template <int MP>
 struct MfmaShape<double, MP> {
     static_assert(MP <= 128, "complex128 matrix-core blocks hold at most 128 members");
     static constexpr bool STREAM = MP == 128;
     static constexpr int RB = 2 * MP / 16;
-    static constexpr int RW = STREAM ? 2 : 1;  // row blocks per wavefront
-    static constexpr int CB = MP == 32 ? 2 : (STREAM ? 2 : 4);
+    static constexpr int RW = STREAM ? RB / 8 : 1;  // row blocks per wavefront
+    static constexpr int CB = MP == 64 ? 4 : 2;
     static constexpr int NT = STREAM ? 16 * CB : 16 * CB * (8 / RB);
     static constexpr int KS = MP / 2;
 };
@@ -230,38 +232,37 @@ __global__ __launch_bounds__(kMfmaBlock) void block_mfma(typename Cx<R>::T* __re
             for (int r = 0; r < 16; ++r)
                 Bs[32 * rb + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)][32 * cb + (lane & 31)] = acc[r];
         } else if constexpr (S::STREAM) {
-            // Wavefront w: row blocks w and w + 8, all CB column blocks. A's
+            // Wavefront w: row blocks w + 8 h (h < RW), all CB column blocks. A's
             // fragment for (row block r, step s) is A[(r * KS + s) * 64 + lane].
-            constexpr int CB = S::CB;
-            f64x4 acc[2][CB];
+            constexpr int CB = S::CB, RW = S::RW;
+            constexpr int KG = 2;  // K steps per group: at 4 the MP = 128 kernel needs 140 VGPRs (one workgroup per CU)
+            f64x4 acc[RW][CB];
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
+            for (int h = 0; h < RW; ++h)
 #pragma unroll
                 for (int c = 0; c < CB; ++c) acc[h][c] = f64x4{0.0, 0.0, 0.0, 0.0};
-            constexpr int KG = 2;  // K steps per group: at 4 the kernel needs 140 VGPRs (one workgroup per CU)
-            const R* __restrict__ A0 = A + (size_t)wave * S::KS * 64 + lane;
-            const R* __restrict__ A1 = A + (size_t)(wave + 8) * S::KS * 64 + lane;
+            const R* __restrict__ Aw = A + (size_t)wave * S::KS * 64 + lane;
 #pragma unroll 4
             for (int s0 = 0; s0 < S::KS; s0 += KG) {
-                double a0[KG], a1[KG], b[KG][CB];
+                double a[KG][RW], b[KG][CB];
 #pragma unroll
                 for (int j = 0; j < KG; ++j) {
-                    a0[j] = A0[(s0 + j) * 64];
-                    a1[j] = A1[(s0 + j) * 64];
+#pragma unroll
+                    for (int h = 0; h < RW; ++h) a[j][h] = Aw[((size_t)8 * h * S::KS + s0 + j) * 64];
 #pragma unroll
                     for (int c = 0; c < CB; ++c) b[j][c] = Bs[4 * (s0 + j) + (lane >> 4)][16 * c + (lane & 15)];
                 }
 #pragma unroll
                 for (int j = 0; j < KG; ++j)
 #pragma unroll
-                    for (int c = 0; c < CB; ++c) {
-                        acc[0][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[j], b[j][c], acc[0][c], 0, 0, 0);
-                        acc[1][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[j], b[j][c], acc[1][c], 0, 0, 0);
-                    }
+                    for (int c = 0; c < CB; ++c)
+#pragma unroll
+                        for (int h = 0; h < RW; ++h)
+                            acc[h][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j][h], b[j][c], acc[h][c], 0, 0, 0);
             }
             __syncthreads();  // every wavefront has read its B fragments
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
+            for (int h = 0; h < RW; ++h)
 #pragma unroll
                 for (int c = 0; c < CB; ++c)
 #pragma unroll
@@ -385,17 +386,19 @@ static void fill_real(const GatePlan& p, const double* U, R* A) {
 
 void fill_mfma_gate(const GatePlan& p, int precision, const double* U, void* dst) {
     const int K2 = 2 * mfma_padded(p.M);
-    if (precision == kC128 && MfmaShape<double, 128>::STREAM && mfma_padded(p.M) == 128) {
+    const bool stream = precision == kC128 && (mfma_padded(p.M) == 128 ? MfmaShape<double, 128>::STREAM
+                                               : (mfma_padded(p.M) == 64 && MfmaShape<double, 64>::STREAM));
+    if (stream) {
         // Fragment order for the streamed kernel: entry (r * KS + s) * 64 + l is
-        // the real form's row 16 r + l mod 16, column 4 s + l / 16.
-        using S = MfmaShape<double, 128>;
+        // the real form's row 16 r + l mod 16, column 4 s + l / 16 (KS = K2 / 4).
+        const int RB = K2 / 16, KS = K2 / 4;
         std::vector<double> rm((size_t)K2 * K2);
         fill_real<double>(p, U, rm.data());
         double* A = static_cast<double*>(dst);
-        for (int r = 0; r < S::RB; ++r)
-            for (int st = 0; st < S::KS; ++st)
+        for (int r = 0; r < RB; ++r)
+            for (int st = 0; st < KS; ++st)
                 for (int l = 0; l < 64; ++l)
-                    A[((size_t)r * S::KS + st) * 64 + l] = rm[(size_t)(16 * r + l % 16) * K2 + 4 * st + l / 16];
+                    A[((size_t)r * KS + st) * 64 + l] = rm[(size_t)(16 * r + l % 16) * K2 + 4 * st + l / 16];
     } else if (precision == kC128) {
         fill_real<double>(p, U, static_cast<double*>(dst));
     } else {
