@@ -240,6 +240,27 @@ def test_reordered_plan_gives_the_same_state_in_the_oracle():
     assert np.max(np.abs(a - b)) < 1e-13
 
 
+def test_lookahead_gathers_same_class_gates():
+    # dense gates on the same classes gather across gates on other qudits
+    # (chain descriptors), but not across a gate controlled on their target
+    from qd_inputs import Gate
+    rng = np.random.default_rng(12)
+    dims = [2, 3, 2, 2]
+    H = lambda q: Gate((q,), haar(dims[q], rng))
+    gates = [H(0), Gate((1,), shift(3)), H(0), Gate((2,), clock(2)), H(0)]
+    _, order = qd.circuit_plan(dims, gates, "c128", reorder=8, with_order=True)
+    assert order == [0, 2, 4, 1, 3]
+    _, order = qd.circuit_plan(dims, gates, "c128", reorder=0, with_order=True)
+    assert order == [0, 1, 2, 3, 4]
+    blocked = [H(0), Gate((1,), shift(3), (0,), (1,)), H(0)]
+    _, order = qd.circuit_plan(dims, blocked, "c128", reorder=8, with_order=True)
+    assert order == [0, 1, 2]
+    shared_control = [Gate((1,), haar(3, rng), (0,), (1,)), Gate((2,), haar(2, rng), (0,), (0,)),
+                      Gate((1,), haar(3, rng), (0,), (1,))]
+    _, order = qd.circuit_plan(dims, shared_control, "c128", reorder=8, with_order=True)
+    assert order == [0, 2, 1]  # sharing only a control qudit commutes
+
+
 def test_reorder_must_not_be_negative():
     from qd_inputs import Gate
     with pytest.raises(qd.QDError):
