@@ -56,6 +56,35 @@ def test_batch_equals_alone_and_oracle(precision):
     runner.close()
 
 
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_batch_with_lookahead_equals_alone(precision):
+    # with a commuting look-ahead every state is planned as it would be alone
+    # with the same options, so the result is again bitwise its solo run
+    rng = np.random.default_rng(26)
+    dims_list = small_specs(rng, 12, 40000)
+    lists = [circuits.random_circuit(d, int(rng.integers(40, 120)), 1300 + i) for i, d in enumerate(dims_list)]
+    psi0 = [rand_state(rng, math.prod(d)) for d in dims_list]
+    runner = qd().batch.BatchRunner(dims_list, precision)
+    for st, p in zip(runner.states, psi0):
+        st.set_amplitudes(p)
+    lazy = runner.run(lists, tile_amps=2048, min_run=32)["rounds"]
+    for st, p in zip(runner.states, psi0):
+        st.set_amplitudes(p)
+    info = runner.run(lists, tile_amps=2048, min_run=32, reorder=64)
+    assert info["rounds"] <= lazy
+    for i, (d, gl, p) in enumerate(zip(dims_list, lists, psi0)):
+        alone = qd().State(d, precision, init=None).set_amplitudes(p)
+        alone.run_circuit(gl, tile_amps=2048, min_run=32, reorder=64)
+        assert np.array_equal(runner.states[i].amplitudes(), alone.amplitudes()), f"state {i}"
+        ref = p.copy() if precision == "c128" else (p.real.astype(np.float32).astype(np.float64) +
+                                                    1j * p.imag.astype(np.float32).astype(np.float64))
+        for g in gl:
+            oracle.apply_gate(d, ref, g)
+        assert_close(runner.states[i].amplitudes(), ref, precision, f"state {i} dims {d}")
+        alone.close()
+    runner.close()
+
+
 def test_batch_rounds_for_whole_register_tiles():
     # registers that fit one tile run their whole circuit in a single round
     rng = np.random.default_rng(22)
