@@ -158,6 +158,22 @@ int qd_state_info(const qd_state* s, uint64_t* D, int32_t* precision, void** dev
 int qd_apply_gate(qd_state* s, const int32_t* targets, int32_t k, const int32_t* controls,
                   const int32_t* values, int32_t m, const double* U);
 
+/* Multi-valued controls (the paper leaves them open after Sec. 2.4): apply U to
+ * targets[0..k-1] on every class whose digit at controls[l] lies in the set
+ * value_masks[l] for every l (bit v of the mask set iff value v is accepted).
+ * A mask must be non-zero and hold only values below the control's dimension;
+ * a control whose mask accepts every value is no condition at all. The classes
+ * of different accepted-value combinations are disjoint, so the update equals
+ * one single-valued controlled gate (qd_apply_gate) per combination, and that
+ * is how it runs: each combination's classes are enumerated directly, so every
+ * accepted amplitude is read and written once and no index is tested against
+ * the sets. Validation as qd_check_gate plus the masks; more than 4096
+ * accepted-value combinations (over the controls that are a condition) give
+ * QD_ERR_NOT_SUPPORTED; on an error nothing is enqueued. In place and
+ * asynchronous, like qd_apply_gate. */
+int qd_apply_gate_masked(qd_state* s, const int32_t* targets, int32_t k, const int32_t* controls,
+                         const uint32_t* value_masks, int32_t m, const double* U);
+
 /* One gate of a gate list: the arguments of qd_apply_gate. */
 typedef struct {
     const int32_t* targets;

@@ -33,12 +33,14 @@ def lib():
         L.oracle_dim.restype = C.c_int64
         L.oracle_init_zero.argtypes = [C.c_int, i32p, f64p]
         L.oracle_apply.argtypes = [C.c_int, i32p, f64p, C.c_int, i32p, C.c_int, i32p, i32p, f64p]
+        L.oracle_apply_masked.argtypes = [C.c_int, i32p, f64p, C.c_int, i32p, C.c_int, i32p,
+                                          np.ctypeslib.ndpointer(np.uint32, flags="C_CONTIGUOUS"), f64p]
         L.oracle_class_members.argtypes = [C.c_int, i32p, C.c_int, i32p, C.c_int, i32p, i32p,
                                            C.c_int64, i64p, i64p, i32p]
         L.oracle_rows.argtypes = [C.c_int, f64p, C.c_int64, f64p, i32p, f64p]
         L.oracle_norm.argtypes = [C.c_int64, f64p, C.POINTER(C.c_double)]
         L.oracle_probabilities.argtypes = [C.c_int64, f64p, f64p]
-        for f in (L.oracle_init_zero, L.oracle_apply, L.oracle_class_members, L.oracle_rows,
+        for f in (L.oracle_init_zero, L.oracle_apply, L.oracle_apply_masked, L.oracle_class_members, L.oracle_rows,
                   L.oracle_norm, L.oracle_probabilities):
             f.restype = C.c_int
         _lib = L
@@ -75,6 +77,18 @@ def apply(dims, psi: np.ndarray, targets, U, controls=(), values=()) -> np.ndarr
         raise TypeError("psi must be a contiguous complex128 array")
     rc = lib().oracle_apply(len(dims), _i32(dims), psi.view(np.float64), len(targets), _i32(targets),
                             len(controls), _i32(controls), _i32(values), _u(U))
+    if rc != 0:
+        raise ValueError("invalid gate")
+    return psi
+
+
+def apply_masked(dims, psi: np.ndarray, targets, U, controls=(), masks=()) -> np.ndarray:
+    """Apply a gate whose control l accepts the values in bit mask masks[l], in place; returns psi."""
+    if psi.dtype != np.complex128 or not psi.flags.c_contiguous:
+        raise TypeError("psi must be a contiguous complex128 array")
+    mk = np.ascontiguousarray(np.asarray(masks, dtype=np.uint32).reshape(-1)) if len(masks) else np.zeros(1, np.uint32)
+    rc = lib().oracle_apply_masked(len(dims), _i32(dims), psi.view(np.float64), len(targets), _i32(targets),
+                                   len(controls), _i32(controls), mk, _u(U))
     if rc != 0:
         raise ValueError("invalid gate")
     return psi

@@ -27,6 +27,10 @@
  *   a = sum_l a_l prod_{l'<l} d_{t_l'} (first target least significant), and
  *   member a of the class with base j sits at j + sum_l a_l s_{t_l}.
  *
+ *   Multi-valued controls (left open by the paper after Sec. 2.4): control k
+ *   accepts a set of values, tested the same way with "in the set" for "equals"
+ *   (oracle_apply_masked).
+ *
  *   Phase and permutation gates (Sec. 2.1, 2.2) are not special-cased: they go
  *   through the same class matvec, whose result is identical for finite inputs.
  *
@@ -159,6 +163,51 @@ int oracle_apply(int n, const int *dims, double *psi, int k, const int *targets,
             if (digit(j, s[targets[l]], dims[targets[l]]) != 0) base = 0;
         /* ... and every control condition holds. */
         if (!base || !controls_hold(j, m, controls, cvals, dims, s)) continue;
+        for (int a = 0; a < M; ++a) {
+            x[2 * a] = psi[2 * (j + off[a])];
+            x[2 * a + 1] = psi[2 * (j + off[a]) + 1];
+        }
+        class_matvec(M, U, x, y);
+        for (int a = 0; a < M; ++a) {
+            psi[2 * (j + off[a])] = y[2 * a];
+            psi[2 * (j + off[a]) + 1] = y[2 * a + 1];
+        }
+    }
+    return 0;
+}
+
+/* Multi-valued controls (the paper leaves them open after Sec. 2.4; read here as:
+ * control l accepts a set V_l of values): |j> satisfies control l iff
+ * floor(j / b_l) mod d_l is in V_l, with V_l given as a bit mask (bit v set iff
+ * v is in V_l). Every index is tested, as in oracle_apply. A mask must be
+ * non-empty and hold only values below d_l. */
+static int controls_hold_masked(int64_t j, int m, const int *controls, const uint32_t *masks, const int *dims,
+                                const int64_t *s) {
+    for (int l = 0; l < m; ++l)
+        if (((masks[l] >> digit(j, s[controls[l]], dims[controls[l]])) & 1u) == 0) return 0;
+    return 1;
+}
+
+int oracle_apply_masked(int n, const int *dims, double *psi, int k, const int *targets, int m,
+                        const int *controls, const uint32_t *masks, const double *U) {
+    int zeros[ORACLE_MAX_QUDITS];
+    int M;
+    if (m < 0 || m > ORACLE_MAX_QUDITS) return -1;
+    memset(zeros, 0, sizeof zeros);
+    if (check_gate(n, dims, k, targets, m, controls, zeros, &M) != 0) return -1;
+    for (int l = 0; l < m; ++l)
+        if (masks[l] == 0 || (masks[l] >> dims[controls[l]]) != 0) return -1;
+    int64_t D = oracle_dim(n, dims);
+    int64_t s[ORACLE_MAX_QUDITS];
+    block_sizes(n, dims, s);
+    int64_t off[ORACLE_MAX_M];
+    for (int a = 0; a < M; ++a) off[a] = local_offset(a, k, targets, dims, s);
+    double x[2 * ORACLE_MAX_M], y[2 * ORACLE_MAX_M];
+    for (int64_t j = 0; j < D; ++j) {
+        int base = 1;
+        for (int l = 0; l < k && base; ++l)
+            if (digit(j, s[targets[l]], dims[targets[l]]) != 0) base = 0;
+        if (!base || !controls_hold_masked(j, m, controls, masks, dims, s)) continue;
         for (int a = 0; a < M; ++a) {
             x[2 * a] = psi[2 * (j + off[a])];
             x[2 * a + 1] = psi[2 * (j + off[a]) + 1];

@@ -73,6 +73,7 @@ def _load() -> C.CDLL:
         "qd_state_get_amplitudes": [vp, f64p, C.c_uint64, C.c_uint64],
         "qd_state_info": [vp, u64p, i32p, C.POINTER(vp)],
         "qd_apply_gate": [vp, i32p, C.c_int32, i32p, i32p, C.c_int32, f64p],
+        "qd_apply_gate_masked": [vp, i32p, C.c_int32, i32p, C.POINTER(C.c_uint32), C.c_int32, f64p],
         "qd_norm": [vp, f64p],
         "qd_probabilities": [vp, f64p, C.c_uint64, C.c_int32],
         "qd_synchronize": [vp],
@@ -267,6 +268,16 @@ class State:
         v, vp_ = _i32(values)
         u, up = _u(U)
         check(lib.qd_apply_gate(self._h, tp, len(targets), cp, vp_, len(controls), up))
+        return self
+
+    def apply_masked(self, targets, U, controls=(), masks=()) -> "State":
+        """Apply U on the classes whose digit at controls[l] is in the set bit mask masks[l] (qd_apply_gate_masked)."""
+        t, tp = _i32(targets)
+        c, cp = _i32(controls)
+        mk = np.ascontiguousarray(np.asarray(list(masks) or [0], dtype=np.uint32))
+        u, up = _u(U)
+        check(lib.qd_apply_gate_masked(self._h, tp, len(targets), cp, mk.ctypes.data_as(C.POINTER(C.c_uint32)),
+                                       len(controls), up))
         return self
 
     def apply_gate(self, g) -> "State":

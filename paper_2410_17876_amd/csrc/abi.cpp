@@ -431,6 +431,62 @@ int qd_apply_gate(qd_state* s, const int32_t* targets, int32_t k, const int32_t*
     return enqueue_single(s, p, U);
 }
 
+static constexpr uint64_t kMaxMaskedCombos = 4096;
+
+int qd_apply_gate_masked(qd_state* s, const int32_t* targets, int32_t k, const int32_t* controls,
+                         const uint32_t* value_masks, int32_t m, const double* U) {
+    if (!s) return set_err(QD_ERR_INVALID_ARGUMENT, "state is null");
+    if (m < 0 || m > QD_MAX_CONTROLS) return set_err(QD_ERR_INVALID_ARGUMENT, "bad number of controls");
+    if (m > 0 && (!controls || !value_masks)) return set_err(QD_ERR_INVALID_ARGUMENT, "controls or masks null");
+    {
+        // the gate's structure (targets, distinct controls, U) as for qd_check_gate, with value 0
+        const int32_t zeros[QD_MAX_CONTROLS] = {};
+        std::string err;
+        int rc = check_gate(s->dims, s->n, targets, k, controls, zeros, m, &err);
+        if (rc) return set_err(rc, err);
+        if (!U) return set_err(QD_ERR_INVALID_ARGUMENT, "U is null");
+    }
+    // Controls that accept every value are dropped; the others list their values.
+    std::vector<int32_t> cq;
+    std::vector<std::vector<int32_t>> vals;
+    for (int l = 0; l < m; ++l) {
+        const int c = controls[l];
+        const uint32_t all = (1u << s->dims[c]) - 1u;
+        if (value_masks[l] == 0 || (value_masks[l] & ~all) != 0)
+            return set_err(QD_ERR_INVALID_ARGUMENT, "a value mask must be non-zero and below the control's dimension");
+        if (value_masks[l] == all) continue;
+        cq.push_back(c);
+        vals.emplace_back();
+        for (int v = 0; v < s->dims[c]; ++v)
+            if ((value_masks[l] >> v) & 1u) vals.back().push_back(v);
+    }
+    // Plan every combination before enqueuing any (an error leaves the state untouched).
+    const int mm = (int)cq.size();
+    uint64_t combos = 1;
+    for (const auto& v : vals)
+        if ((combos *= v.size()) > kMaxMaskedCombos)
+            return set_err(QD_ERR_NOT_SUPPORTED, "more than 4096 accepted-value combinations");
+    std::vector<int> idx(mm, 0);
+    std::vector<GatePlan> plans;
+    std::vector<int32_t> cv(mm > 0 ? mm : 1);
+    while (true) {
+        for (int l = 0; l < mm; ++l) cv[l] = vals[l][idx[l]];
+        plans.emplace_back();
+        std::string err;
+        int rc = plan_gate(s->dims, s->n, targets, k, mm ? cq.data() : nullptr, mm ? cv.data() : nullptr, mm, U,
+                           &plans.back(), &err);
+        if (rc) return set_err(rc, err);
+        int l = 0;
+        while (l < mm && ++idx[l] == (int)vals[l].size()) idx[l++] = 0;
+        if (l == mm) break;
+    }
+    int rc = use_device(s);
+    if (rc) return rc;
+    for (const GatePlan& p : plans)
+        if ((rc = enqueue_single(s, p, U))) return rc;
+    return QD_OK;
+}
+
 int qd_circuit_plan(const int32_t* dims, int32_t n, int32_t precision, const qd_gate_desc* gates, int32_t count,
                     const qd_circuit_options* opts, int32_t* pass_gates, int32_t* pass_tile, int32_t* order,
                     int32_t* npasses) {
