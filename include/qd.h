@@ -227,6 +227,34 @@ int qd_circuit_plan(const int32_t* dims, int32_t n, int32_t precision, const qd_
                     const qd_circuit_options* opts, int32_t* pass_gates, int32_t* pass_tile, int32_t* order,
                     int32_t* npasses);
 
+/* ---- sparse statevectors ---------------------------------------------------------- */
+
+/* The sparse form of the method (Sec. 3: GHZ states of up to 62 qubits, 39
+ * qutrits, 31 ququads, 27 ququints): only the nonzero amplitudes are kept, as
+ * (basis index, complex128 amplitude) pairs in device memory sorted by index.
+ * A gate groups the entries by class (Sec. 2.3), applies U to every class that
+ * has a nonzero member (absent members are 0), keeps the nonzero results and
+ * leaves entries whose controls do not hold (Sec. 2.4) unchanged. Calls are
+ * synchronous and use the device that was current at creation. */
+typedef struct qd_sparse qd_sparse;
+
+/* |0...0> on the register (validation as qd_dim). */
+int qd_sparse_create(const int32_t* dims, int32_t n, qd_sparse** out);
+int qd_sparse_destroy(qd_sparse* s);
+
+/* Apply U (M x M, row-major [out][in], interleaved FP64) to targets[0..k-1],
+ * controlled on controls[l] holding values[l]. Validation as qd_check_gate;
+ * M at most 16 (else QD_ERR_NOT_SUPPORTED). On an error the state is unchanged. */
+int qd_sparse_apply_gate(qd_sparse* s, const int32_t* targets, int32_t k, const int32_t* controls,
+                         const int32_t* values, int32_t m, const double* U);
+
+/* Number of stored (nonzero) amplitudes. */
+int qd_sparse_nnz(const qd_sparse* s, uint64_t* nnz);
+
+/* Copy the first min(cap, nnz) entries, in increasing basis index, to host
+ * arrays keys[cap] and amps[2 * cap] (interleaved re, im). */
+int qd_sparse_get(const qd_sparse* s, uint64_t* keys, double* amps, uint64_t cap);
+
 /* ---- batches of independent states ---------------------------------------------- */
 
 /* A batch context holds the staging buffers of qd_batch_apply for one precision.

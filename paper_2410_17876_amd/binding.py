@@ -74,6 +74,11 @@ def _load() -> C.CDLL:
         "qd_state_info": [vp, u64p, i32p, C.POINTER(vp)],
         "qd_apply_gate": [vp, i32p, C.c_int32, i32p, i32p, C.c_int32, f64p],
         "qd_apply_gate_masked": [vp, i32p, C.c_int32, i32p, C.POINTER(C.c_uint32), C.c_int32, f64p],
+        "qd_sparse_create": [i32p, C.c_int32, C.POINTER(vp)],
+        "qd_sparse_destroy": [vp],
+        "qd_sparse_apply_gate": [vp, i32p, C.c_int32, i32p, i32p, C.c_int32, f64p],
+        "qd_sparse_nnz": [vp, u64p],
+        "qd_sparse_get": [vp, u64p, f64p, C.c_uint64],
         "qd_norm": [vp, f64p],
         "qd_probabilities": [vp, f64p, C.c_uint64, C.c_int32],
         "qd_synchronize": [vp],
@@ -363,6 +368,52 @@ def _batch_args(states, gate_lists):
     gp = (C.POINTER(GateDesc) * max(1, n))(*[C.cast(g.descs, C.POINTER(GateDesc)) for g in gls])
     counts = np.array([len(g) for g in gls] or [0], dtype=np.int32)
     return gls, hs, gp, counts
+
+
+class SparseState:
+    """A sparse statevector (qd_sparse_*): nonzero amplitudes as (basis index, complex128) pairs on the GPU."""
+
+    def __init__(self, dims):
+        self.dims = [int(d) for d in dims]
+        d, dp = _i32(self.dims)
+        self._h = C.c_void_p()
+        check(lib.qd_sparse_create(dp, len(self.dims), C.byref(self._h)))
+
+    def apply(self, targets, U, controls=(), values=()) -> "SparseState":
+        t, tp = _i32(targets)
+        c, cp = _i32(controls)
+        v, vp_ = _i32(values)
+        u, up = _u(U)
+        check(lib.qd_sparse_apply_gate(self._h, tp, len(targets), cp, vp_, len(controls), up))
+        return self
+
+    def apply_gate(self, g) -> "SparseState":
+        return self.apply(g.targets, g.U, g.controls, g.values)
+
+    def nnz(self) -> int:
+        out = C.c_uint64()
+        check(lib.qd_sparse_nnz(self._h, C.byref(out)))
+        return out.value
+
+    def entries(self):
+        """(keys uint64, amplitudes complex128), in increasing basis index."""
+        n = self.nnz()
+        keys = np.zeros(max(1, n), dtype=np.uint64)
+        amps = np.zeros(2 * max(1, n), dtype=np.float64)
+        check(lib.qd_sparse_get(self._h, keys.ctypes.data_as(C.POINTER(C.c_uint64)),
+                                amps.ctypes.data_as(C.POINTER(C.c_double)), n))
+        return keys[:n], amps.view(np.complex128)[:n]
+
+    def close(self) -> None:
+        if self._h:
+            lib.qd_sparse_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class BatchPlan:

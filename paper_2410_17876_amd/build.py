@@ -18,7 +18,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libqd.so")
 ARCH = os.environ.get("QD_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["abi.cpp", "planner.cpp", "fusion.cpp", "sweep.hip", "fused.hip", "mfma.hip", "reduce.hip"]
+SOURCES = ["abi.cpp", "planner.cpp", "fusion.cpp", "sweep.hip", "fused.hip", "mfma.hip", "reduce.hip", "sparse.hip"]
 
 CFLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -17,6 +17,7 @@
 #include "kernels.h"
 #include "plan.h"
 #include "planner.h"
+#include "sparse.h"
 
 using namespace qd;
 
@@ -429,6 +430,111 @@ int qd_apply_gate(qd_state* s, const int32_t* targets, int32_t k, const int32_t*
     rc = use_device(s);
     if (rc) return rc;
     return enqueue_single(s, p, U);
+}
+
+struct qd_sparse {
+    int n = 0;
+    int32_t dims[QD_MAX_QUDITS] = {};
+    uint64_t s[QD_MAX_QUDITS] = {};
+    int device = 0;
+    qd::SparseData d;
+};
+
+int qd_sparse_create(const int32_t* dims, int32_t n, qd_sparse** out) {
+    if (!out) return set_err(QD_ERR_INVALID_ARGUMENT, "out is null");
+    *out = nullptr;
+    std::string err;
+    uint64_t D = 0;
+    int rc = check_dims(dims, n, &D, &err);
+    if (rc) return set_err(rc, err);
+    qd_sparse* s = new qd_sparse;
+    s->n = n;
+    uint64_t st = 1;
+    for (int i = 0; i < n; ++i) {
+        s->dims[i] = dims[i];
+        s->s[i] = st;
+        st *= (uint64_t)dims[i];
+    }
+    hipError_t e = hipGetDevice(&s->device);
+    const uint64_t key0 = 0;
+    const double amp0[2] = {1.0, 0.0};
+    if (e == hipSuccess) e = hipMalloc((void**)&s->d.keys, 8);
+    if (e == hipSuccess) e = hipMalloc((void**)&s->d.amps, 16);
+    if (e == hipSuccess) e = hipMemcpy(s->d.keys, &key0, 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(s->d.amps, amp0, 16, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        if (s->d.keys) (void)hipFree(s->d.keys);
+        if (s->d.amps) (void)hipFree(s->d.amps);
+        delete s;
+        return set_err(QD_ERR_DEVICE, std::string("sparse state: ") + hipGetErrorString(e));
+    }
+    s->d.nnz = 1;
+    *out = s;
+    return QD_OK;
+}
+
+int qd_sparse_destroy(qd_sparse* s) {
+    if (!s) return QD_OK;
+    (void)hipSetDevice(s->device);
+    if (s->d.keys) (void)hipFree(s->d.keys);
+    if (s->d.amps) (void)hipFree(s->d.amps);
+    delete s;
+    return QD_OK;
+}
+
+int qd_sparse_apply_gate(qd_sparse* s, const int32_t* targets, int32_t k, const int32_t* controls,
+                         const int32_t* values, int32_t m, const double* U) {
+    if (!s) return set_err(QD_ERR_INVALID_ARGUMENT, "state is null");
+    std::string err;
+    int rc = check_gate(s->dims, s->n, targets, k, controls, values, m, &err);
+    if (rc) return set_err(rc, err);
+    if (!U) return set_err(QD_ERR_INVALID_ARGUMENT, "U is null");
+    qd::SparseGate g;
+    std::memset(&g, 0, sizeof g);
+    g.k = k;
+    g.M = 1;
+    for (int l = 0; l < k; ++l) {
+        g.ts[l] = s->s[targets[l]];
+        g.td[l] = (uint32_t)s->dims[targets[l]];
+        g.M *= s->dims[targets[l]];
+    }
+    if (g.M > qd::kSparseMaxM) return set_err(QD_ERR_NOT_SUPPORTED, "sparse gates act on at most 16 amplitudes");
+    g.m = m;
+    for (int l = 0; l < m; ++l) {
+        g.cs[l] = s->s[controls[l]];
+        g.cd[l] = (uint32_t)s->dims[controls[l]];
+        g.cv[l] = (uint32_t)values[l];
+    }
+    for (int a = 0; a < g.M; ++a) {
+        uint64_t off = 0;
+        int r = a;
+        for (int l = 0; l < k; ++l) {
+            off += (uint64_t)(r % (int)g.td[l]) * g.ts[l];
+            r /= (int)g.td[l];
+        }
+        g.off[a] = off;
+    }
+    hipError_t e = hipSetDevice(s->device);
+    if (e == hipSuccess) e = qd::sparse_apply(s->d, g, U);
+    if (e != hipSuccess) return set_err(QD_ERR_DEVICE, std::string("sparse gate: ") + hipGetErrorString(e));
+    return QD_OK;
+}
+
+int qd_sparse_nnz(const qd_sparse* s, uint64_t* nnz) {
+    if (!s || !nnz) return set_err(QD_ERR_INVALID_ARGUMENT, "null argument");
+    *nnz = s->d.nnz;
+    return QD_OK;
+}
+
+int qd_sparse_get(const qd_sparse* s, uint64_t* keys, double* amps, uint64_t cap) {
+    if (!s || (cap && (!keys || !amps))) return set_err(QD_ERR_INVALID_ARGUMENT, "null argument");
+    const uint64_t c = std::min<uint64_t>(cap, s->d.nnz);
+    if (c == 0) return QD_OK;
+    hipError_t e = hipSetDevice(s->device);
+    if (e == hipSuccess) e = hipMemcpy(keys, s->d.keys, c * 8, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(amps, s->d.amps, c * 16, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return set_err(QD_ERR_DEVICE, std::string("sparse get: ") + hipGetErrorString(e));
+    return QD_OK;
 }
 
 static constexpr uint64_t kMaxMaskedCombos = 4096;
