@@ -32,8 +32,8 @@ Also reported: the in-place read+rewrite copy ceiling measured on the same
 buffer (qd_copy_ceiling), and the FP64 oracle (one thread) on the first gates
 of the same circuit and state as the CPU baseline. Further runs under `runs`:
 the 12-ququint workload (300 Haar gates of 25 and 125 members, MFMA) in
-complex64 and complex128, the 512-circuit batched workload and the served
-workload.
+complex64 and complex128, the 512-circuit batched workload, the sparse GHZ
+builds and the served workload.
 """
 from __future__ import annotations
 
@@ -356,6 +356,52 @@ def run_served(qd, n_closed, n_open, loads, lookahead):
             "lookahead": lookahead}
 
 
+GHZ_REGISTERS = ((2, 62), (3, 39), (4, 31), (5, 27))
+
+
+def ghz_gates(d, n):
+    from qd_inputs import Gate, dft, shift
+    return [Gate((0,), dft(d))] + [Gate((q,), shift(d, v), (0,), (v,)) for q in range(1, n) for v in range(1, d)]
+
+
+def cpu_baseline_sparse():
+    """The sparse oracle (plain Python, one thread) on the same GHZ builds, in ms."""
+    from oracle import sparse as soracle
+    out = {}
+    for d, n in GHZ_REGISTERS:
+        t0 = time.perf_counter()
+        soracle.run([d] * n, ghz_gates(d, n))
+        out[f"{d}^{n}"] = round(1e3 * (time.perf_counter() - t0), 3)
+    return out
+
+
+def run_sparse_ghz(qd, reps=3):
+    """The sparse variant on the paper's GHZ registers: GHZ_d on 62 qubits, 39
+    qutrits, 31 ququads and 27 ququints (DFT on q0, then X_{+v} on each other
+    qudit controlled on q0 = v), from |0...0>."""
+    out = {}
+    for d, n in GHZ_REGISTERS:
+        gates = ghz_gates(d, n)
+        best = None
+        for rep in range(reps + 1):  # the first build warms up
+            st = qd.SparseState([d] * n)
+            t0 = time.perf_counter()
+            for g in gates:
+                st.apply_gate(g)
+            dt = time.perf_counter() - t0
+            nnz = st.nnz()
+            st.close()
+            if rep and (best is None or dt < best):
+                best = dt
+        out[f"{d}^{n}"] = {"gates": len(gates), "nnz": nnz, "ms": round(1e3 * best, 3),
+                           "gates_per_s": round(len(gates) / best, 1)}
+        log(f"sparse GHZ_{d} on {n} qudits: {len(gates)} gates in {1e3 * best:.2f} ms")
+    return {"workload": "GHZ_d from |0...0> on 62 qubits, 39 qutrits, 31 ququads, 27 ququints (sparse, complex128)",
+            "path": "qd_sparse_apply_gate: classify, radix sort by class, one thread per class, keep nonzeros; "
+                    "synchronous, so launch and sort latency bound",
+            "registers": out}
+
+
 def cpu_baseline(qd, dims, gates, psi, seconds):
     import oracle
 
@@ -387,6 +433,7 @@ def main() -> int:
     ap.add_argument("--no-c64", action="store_true", help="skip the complex64 runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ququint", action="store_true", help="skip the 12-ququint MFMA workloads")
+    ap.add_argument("--no-sparse", action="store_true", help="skip the sparse GHZ builds")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-circuit batched workload")
     ap.add_argument("--no-served", action="store_true", help="skip the served (continuous batching) workload")
     ap.add_argument("--served-closed", type=int, default=600,
@@ -462,6 +509,8 @@ def main() -> int:
     if not args.no_batched:
         for p in (["c64", "c128"] if not args.no_c64 else ["c128"]):
             res[f"batched_{p}"] = run_batched(qd, p, args.steps, args.warmup, args.tune_cache, args.lookahead)
+    if not args.no_sparse:
+        res["sparse"] = run_sparse_ghz(qd)
     if not args.no_served:
         res["served"] = run_served(qd, args.served_closed, args.served_open,
                                    [float(x) for x in args.served_loads.split(",")], args.lookahead)
@@ -469,6 +518,8 @@ def main() -> int:
     if host is not None:
         cpu = cpu_baseline(qd, dims, gates, host, args.cpu_seconds)
         log(f"cpu baseline: {cpu['value']:.3e} updates/s ({cpu['sample']})")
+        if "sparse" in res:
+            res["sparse"]["cpu_oracle_ms"] = cpu_baseline_sparse()
 
     head_mode = modes[0]
     h = res["c128"][head_mode]
@@ -512,6 +563,8 @@ def main() -> int:
             "value": r["value"], "unit": "updates/s", "dtype": "f64", "ms_per_step": r["ms_per_step"],
             "launches_per_step": r["launches_per_step"], "roofline": r["roofline"],
             "norm_last_step": r["norm_last_step"], "kernels": r["kernels"]}
+    if "sparse" in res:
+        line["runs"]["sparse_ghz_c128"] = res["sparse"]
     if "served" in res:
         line["runs"]["served_c64"] = res["served"]
     for p in ("c64", "c128"):
