@@ -456,19 +456,12 @@ int qd_sparse_create(const int32_t* dims, int32_t n, qd_sparse** out) {
         st *= (uint64_t)dims[i];
     }
     hipError_t e = hipGetDevice(&s->device);
-    const uint64_t key0 = 0;
-    const double amp0[2] = {1.0, 0.0};
-    if (e == hipSuccess) e = hipMalloc((void**)&s->d.keys, 8);
-    if (e == hipSuccess) e = hipMalloc((void**)&s->d.amps, 16);
-    if (e == hipSuccess) e = hipMemcpy(s->d.keys, &key0, 8, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(s->d.amps, amp0, 16, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = qd::sparse_init(s->d);
     if (e != hipSuccess) {
-        if (s->d.keys) (void)hipFree(s->d.keys);
-        if (s->d.amps) (void)hipFree(s->d.amps);
+        qd::sparse_release(s->d);
         delete s;
         return set_err(QD_ERR_DEVICE, std::string("sparse state: ") + hipGetErrorString(e));
     }
-    s->d.nnz = 1;
     *out = s;
     return QD_OK;
 }
@@ -476,8 +469,7 @@ int qd_sparse_create(const int32_t* dims, int32_t n, qd_sparse** out) {
 int qd_sparse_destroy(qd_sparse* s) {
     if (!s) return QD_OK;
     (void)hipSetDevice(s->device);
-    if (s->d.keys) (void)hipFree(s->d.keys);
-    if (s->d.amps) (void)hipFree(s->d.amps);
+    qd::sparse_release(s->d);
     delete s;
     return QD_OK;
 }

@@ -29,16 +29,28 @@ struct SparseGate {
     uint64_t off[kSparseMaxM];        // member offsets: off[a] = sum_l a_l ts[l]
 };
 
-// Device arrays of a sparse state; nnz entries, keys strictly increasing.
+// Device arrays of a sparse state; nnz entries, keys strictly increasing. The
+// entries live in one of two slots (the other receives the next gate's result),
+// and a gate's temporaries in a workspace; all three only grow, so a gate
+// allocates nothing once the state has reached its size.
 struct SparseData {
     uint64_t nnz = 0;
     uint64_t* keys = nullptr;
     double2* amps = nullptr;
+    void* slot[2] = {nullptr, nullptr};
+    size_t slot_bytes[2] = {0, 0};
+    int cur = 0;              // slot holding keys/amps
+    void* work = nullptr;
+    size_t work_bytes = 0;
 };
 
-// Replace `d` by the result of applying g (U: M x M complex, row-major
-// [out][in], interleaved FP64) on the null stream; synchronous. Frees the old
-// arrays on success; on an error `d` is unchanged.
+// Replace `d`'s entries by the result of applying g (U: M x M complex,
+// row-major [out][in], interleaved FP64) on the null stream; synchronous. On an
+// error the entries are unchanged.
 hipError_t sparse_apply(SparseData& d, const SparseGate& g, const double* U);
+
+// Set `d` to the single entry |0...0> with amplitude 1; frees everything with release.
+hipError_t sparse_init(SparseData& d);
+void sparse_release(SparseData& d);
 
 }  // namespace qd

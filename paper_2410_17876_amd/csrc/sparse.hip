@@ -14,6 +14,8 @@
 
 #include <hipcub/hipcub.hpp>
 
+#include <algorithm>
+
 #include "sparse.h"
 
 namespace qd {
@@ -102,113 +104,144 @@ __global__ void iota_u32(uint32_t* p, uint64_t n) {
     if (i < n) p[i] = (uint32_t)i;
 }
 
-// Device buffers freed on scope exit.
-struct Pool {
-    void* p[32] = {};  // one gate takes 19 buffers
-    int n = 0;
-    hipError_t get(void** out, size_t bytes) {
-        *out = nullptr;
-        hipError_t e = hipMalloc(out, bytes ? bytes : 1);
-        if (e == hipSuccess) p[n++] = *out;
-        return e;
-    }
-    void release(void* q) {
-        for (int i = 0; i < n; ++i)
-            if (p[i] == q) p[i] = nullptr;
-    }
-    ~Pool() {
-        for (int i = 0; i < n; ++i)
-            if (p[i]) (void)hipFree(p[i]);
+unsigned blocks(uint64_t n) { return (unsigned)((n + 255) / 256); }
+
+size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Carves 256-byte aligned pieces out of one buffer (first pass: only sums the sizes).
+struct Carver {
+    unsigned char* base;
+    size_t used = 0;
+    template <typename T>
+    T* take(size_t bytes) {
+        T* p = base ? reinterpret_cast<T*>(base + used) : nullptr;
+        used += up256(bytes ? bytes : 1);
+        return p;
     }
 };
 
-unsigned blocks(uint64_t n) { return (unsigned)((n + 255) / 256); }
+hipError_t grow(void** buf, size_t* have, size_t need) {
+    if (*have >= need) return hipSuccess;
+    void* p = nullptr;
+    const size_t want = need + need / 2;
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) return e;
+    if (*buf) (void)hipFree(*buf);
+    *buf = p;
+    *have = want;
+    return hipSuccess;
+}
 
 }  // namespace
+
+hipError_t sparse_init(SparseData& d) {
+    size_t have = d.slot_bytes[0];
+    hipError_t e = grow(&d.slot[0], &have, 256 + 16);
+    if (e != hipSuccess) return e;
+    d.slot_bytes[0] = have;
+    d.cur = 0;
+    d.keys = static_cast<uint64_t*>(d.slot[0]);
+    d.amps = reinterpret_cast<double2*>(static_cast<unsigned char*>(d.slot[0]) + 256);
+    const uint64_t key0 = 0;
+    const double2 amp0{1.0, 0.0};
+    if ((e = hipMemcpy(d.keys, &key0, 8, hipMemcpyHostToDevice)) != hipSuccess) return e;
+    if ((e = hipMemcpy(d.amps, &amp0, 16, hipMemcpyHostToDevice)) != hipSuccess) return e;
+    d.nnz = 1;
+    return hipSuccess;
+}
+
+void sparse_release(SparseData& d) {
+    for (int i = 0; i < 2; ++i)
+        if (d.slot[i]) (void)hipFree(d.slot[i]);
+    if (d.work) (void)hipFree(d.work);
+    d = SparseData{};
+}
 
 hipError_t sparse_apply(SparseData& d, const SparseGate& g, const double* U) {
     const uint64_t n = d.nnz;
     if (n == 0) return hipSuccess;
     if (n > 0xFFFFFFFFull / (uint64_t)g.M) return hipErrorInvalidValue;
-    Pool pool;
+    const uint64_t cap = n * (uint64_t)g.M;
     hipError_t e;
-    uint64_t *group, *sgroup;
-    int32_t* local;
-    uint32_t *idx, *sidx;
-    double2* dU;
 #define QD_TRY(x) \
     if ((e = (x)) != hipSuccess) return e
-    QD_TRY(pool.get((void**)&group, n * 8));
-    QD_TRY(pool.get((void**)&sgroup, n * 8));
-    QD_TRY(pool.get((void**)&local, n * 4));
-    QD_TRY(pool.get((void**)&idx, n * 4));
-    QD_TRY(pool.get((void**)&sidx, n * 4));
-    QD_TRY(pool.get((void**)&dU, (size_t)g.M * g.M * 16));
+    // Temporary storage of the three library calls, at their largest sizes.
+    size_t tb_sort1 = 0, tb_sel = 0, tb_sort2 = 0;
+    QD_TRY(hipcub::DeviceRadixSort::SortPairs(nullptr, tb_sort1, (uint64_t*)nullptr, (uint64_t*)nullptr,
+                                              (uint32_t*)nullptr, (uint32_t*)nullptr, (int)n));
+    QD_TRY(hipcub::DeviceSelect::Flagged(nullptr, tb_sel, (uint64_t*)nullptr, (uint8_t*)nullptr,
+                                         (uint64_t*)nullptr, (int*)nullptr, (int)cap));
+    QD_TRY(hipcub::DeviceRadixSort::SortPairs(nullptr, tb_sort2, (uint64_t*)nullptr, (uint64_t*)nullptr,
+                                              (uint32_t*)nullptr, (uint32_t*)nullptr, (int)cap));
+    const size_t tb = std::max(tb_sort1, std::max(tb_sel, tb_sort2));
+    auto carve = [&](Carver& c, uint64_t** group, uint64_t** sgroup, int32_t** local, uint32_t** idx,
+                     uint32_t** sidx, double2** dU, void** temp, uint64_t** okeys, double2** oamps, uint8_t** oflag,
+                     uint32_t** pos, uint32_t** kpos, uint32_t** spos, uint64_t** kkeys, int** nsel) {
+        *group = c.take<uint64_t>(n * 8);
+        *sgroup = c.take<uint64_t>(n * 8);
+        *local = c.take<int32_t>(n * 4);
+        *idx = c.take<uint32_t>(n * 4);
+        *sidx = c.take<uint32_t>(n * 4);
+        *dU = c.take<double2>((size_t)g.M * g.M * 16);
+        *temp = c.take<void>(tb);
+        *okeys = c.take<uint64_t>(cap * 8);
+        *oamps = c.take<double2>(cap * 16);
+        *oflag = c.take<uint8_t>(cap);
+        *pos = c.take<uint32_t>(cap * 4);
+        *kpos = c.take<uint32_t>(cap * 4);
+        *spos = c.take<uint32_t>(cap * 4);
+        *kkeys = c.take<uint64_t>(cap * 8);
+        *nsel = c.take<int>(sizeof(int));
+    };
+    uint64_t *group, *sgroup, *okeys, *kkeys;
+    int32_t* local;
+    uint32_t *idx, *sidx, *pos, *kpos, *spos;
+    double2 *dU, *oamps;
+    uint8_t* oflag;
+    void* temp;
+    int* nsel;
+    Carver sizing{nullptr};
+    carve(sizing, &group, &sgroup, &local, &idx, &sidx, &dU, &temp, &okeys, &oamps, &oflag, &pos, &kpos, &spos,
+          &kkeys, &nsel);
+    QD_TRY(grow(&d.work, &d.work_bytes, sizing.used));
+    Carver c{static_cast<unsigned char*>(d.work)};
+    carve(c, &group, &sgroup, &local, &idx, &sidx, &dU, &temp, &okeys, &oamps, &oflag, &pos, &kpos, &spos, &kkeys,
+          &nsel);
+
     QD_TRY(hipMemcpy(dU, U, (size_t)g.M * g.M * 16, hipMemcpyHostToDevice));
     hipLaunchKernelGGL(sparse_classify, dim3(blocks(n)), dim3(256), 0, 0, d.keys, n, g, group, local, idx);
     QD_TRY(hipGetLastError());
-    size_t tb = 0;
-    void* temp = nullptr;
-    QD_TRY(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, group, sgroup, idx, sidx, (int)n));
-    QD_TRY(pool.get(&temp, tb));
-    QD_TRY(hipcub::DeviceRadixSort::SortPairs(temp, tb, group, sgroup, idx, sidx, (int)n));
-
-    const uint64_t cap = n * (uint64_t)g.M;
-    uint64_t* okeys;
-    double2* oamps;
-    uint8_t* oflag;
-    QD_TRY(pool.get((void**)&okeys, cap * 8));
-    QD_TRY(pool.get((void**)&oamps, cap * 16));
-    QD_TRY(pool.get((void**)&oflag, cap));
+    size_t t1 = tb;
+    QD_TRY(hipcub::DeviceRadixSort::SortPairs(temp, t1, group, sgroup, idx, sidx, (int)n));
     hipLaunchKernelGGL(sparse_classes, dim3(blocks(n)), dim3(256), 0, 0, sgroup, sidx, n, local, d.amps, dU, g,
                        okeys, oamps, oflag);
     QD_TRY(hipGetLastError());
-
-    // Keep the flagged results: keys with their positions, then the positions sorted by key.
-    uint32_t *pos, *kpos, *spos;
-    uint64_t* kkeys;
-    int* nsel;
-    QD_TRY(pool.get((void**)&pos, cap * 4));
-    QD_TRY(pool.get((void**)&kpos, cap * 4));
-    QD_TRY(pool.get((void**)&kkeys, cap * 8));
-    QD_TRY(pool.get((void**)&nsel, sizeof(int)));
+    // Keep the flagged results (keys, and their positions), then sort them by key.
     hipLaunchKernelGGL(iota_u32, dim3(blocks(cap)), dim3(256), 0, 0, pos, cap);
     QD_TRY(hipGetLastError());
-    size_t tb2 = 0;
-    void* temp2 = nullptr;
-    QD_TRY(hipcub::DeviceSelect::Flagged(nullptr, tb2, okeys, oflag, kkeys, nsel, (int)cap));
-    QD_TRY(pool.get(&temp2, tb2));
-    QD_TRY(hipcub::DeviceSelect::Flagged(temp2, tb2, okeys, oflag, kkeys, nsel, (int)cap));
-    QD_TRY(hipcub::DeviceSelect::Flagged(temp2, tb2, pos, oflag, kpos, nsel, (int)cap));
+    size_t t2 = tb;
+    QD_TRY(hipcub::DeviceSelect::Flagged(temp, t2, okeys, oflag, kkeys, nsel, (int)cap));
+    t2 = tb;
+    QD_TRY(hipcub::DeviceSelect::Flagged(temp, t2, pos, oflag, kpos, nsel, (int)cap));
     int h_sel = 0;
     QD_TRY(hipMemcpy(&h_sel, nsel, sizeof(int), hipMemcpyDeviceToHost));
     const uint64_t m = (uint64_t)h_sel;
 
-    uint64_t* nkeys;
-    double2* namps;
-    void* nk = nullptr;
-    void* na = nullptr;
-    QD_TRY(pool.get(&nk, m * 8));
-    QD_TRY(pool.get(&na, m * 16));
-    nkeys = static_cast<uint64_t*>(nk);
-    namps = static_cast<double2*>(na);
+    // The result goes to the other slot.
+    const int nxt = d.cur ^ 1;
+    const size_t kbytes = up256(m * 8 + 1);
+    QD_TRY(grow(&d.slot[nxt], &d.slot_bytes[nxt], kbytes + m * 16 + 16));
+    uint64_t* nkeys = static_cast<uint64_t*>(d.slot[nxt]);
+    double2* namps = reinterpret_cast<double2*>(static_cast<unsigned char*>(d.slot[nxt]) + kbytes);
     if (m > 0) {
-        QD_TRY(pool.get((void**)&spos, m * 4));
-        size_t tb3 = 0;
-        void* temp3 = nullptr;
-        QD_TRY(hipcub::DeviceRadixSort::SortPairs(nullptr, tb3, kkeys, nkeys, kpos, spos, (int)m));
-        QD_TRY(pool.get(&temp3, tb3));
-        QD_TRY(hipcub::DeviceRadixSort::SortPairs(temp3, tb3, kkeys, nkeys, kpos, spos, (int)m));
+        size_t t3 = tb;
+        QD_TRY(hipcub::DeviceRadixSort::SortPairs(temp, t3, kkeys, nkeys, kpos, spos, (int)m));
         hipLaunchKernelGGL(gather_amps, dim3(blocks(m)), dim3(256), 0, 0, spos, oamps, m, namps);
         QD_TRY(hipGetLastError());
     }
     QD_TRY(hipDeviceSynchronize());
 #undef QD_TRY
-    // Success: the new arrays replace the old ones.
-    pool.release(nk);
-    pool.release(na);
-    (void)hipFree(d.keys);
-    (void)hipFree(d.amps);
+    d.cur = nxt;
     d.keys = nkeys;
     d.amps = namps;
     d.nnz = m;
