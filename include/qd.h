@@ -244,7 +244,8 @@ int qd_sparse_destroy(qd_sparse* s);
 
 /* Apply U (M x M, row-major [out][in], interleaved FP64) to targets[0..k-1],
  * controlled on controls[l] holding values[l]. Validation as qd_check_gate;
- * M at most 16 (else QD_ERR_NOT_SUPPORTED). On an error the state is unchanged. */
+ * M at most 16 and (stored entries) x M below 2^31 (else QD_ERR_NOT_SUPPORTED).
+ * On an error the state is unchanged. */
 int qd_sparse_apply_gate(qd_sparse* s, const int32_t* targets, int32_t k, const int32_t* controls,
                          const int32_t* values, int32_t m, const double* U);
 

@@ -491,6 +491,8 @@ int qd_sparse_apply_gate(qd_sparse* s, const int32_t* targets, int32_t k, const 
         g.M *= s->dims[targets[l]];
     }
     if (g.M > qd::kSparseMaxM) return set_err(QD_ERR_NOT_SUPPORTED, "sparse gates act on at most 16 amplitudes");
+    if (s->d.nnz > (uint64_t)INT32_MAX / (uint64_t)g.M)
+        return set_err(QD_ERR_NOT_SUPPORTED, "sparse state too large: stored entries x class size must stay below 2^31");
     g.m = m;
     for (int l = 0; l < m; ++l) {
         g.cs[l] = s->s[controls[l]];

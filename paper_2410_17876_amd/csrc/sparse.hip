@@ -160,7 +160,8 @@ void sparse_release(SparseData& d) {
 hipError_t sparse_apply(SparseData& d, const SparseGate& g, const double* U) {
     const uint64_t n = d.nnz;
     if (n == 0) return hipSuccess;
-    if (n > 0xFFFFFFFFull / (uint64_t)g.M) return hipErrorInvalidValue;
+    // hipCUB counts items in int: the M results per entry must stay below 2^31
+    if (n > (uint64_t)INT32_MAX / (uint64_t)g.M) return hipErrorInvalidValue;
     const uint64_t cap = n * (uint64_t)g.M;
     hipError_t e;
 #define QD_TRY(x) \
