@@ -8,7 +8,7 @@ Gaussian initial state (seed 1001) resident in HBM, and a 500-gate circuit: w.p.
 controlled X 20%). One step = the whole circuit applied once, then the FP64
 norm. Six runs of the same circuit:
 
-  lookahead c128  qd_apply_circuit with LDS-staged fusion and a 128-gate
+  lookahead c128  qd_apply_circuit with LDS-staged fusion and a 256-gate
                   commuting look-ahead (a pass also takes later gates that
                   commute with the ones it skips) -- the headline `value`
   fused c128      the same passes strictly in the given order (the library's
@@ -93,7 +93,7 @@ TILE = {"c128": 0, "c64": 0}
 MIN_RUN = {"c128": 0, "c64": 0}
 # Look-ahead of the planner in "lookahead" mode: a pass also takes later gates
 # that commute with the ones it skips (qd_circuit_options.reorder).
-LOOKAHEAD = 128
+LOOKAHEAD = 256
 
 
 def build_units(qd, dims, gates, precision, mode):
