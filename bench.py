@@ -69,16 +69,29 @@ def kernel_key(info: dict, precision: str) -> str:
     return f"{info['kernel']}<{t},M={info['M']}>"
 
 
-def source_digest() -> str:
+# The sources each kernel family (and the planner that shapes its launches) is
+# built from: counter readings stay valid while these files are unchanged.
+KERNEL_SOURCES = {
+    "fused_tile": ["fused.hip", "fused.h", "device.h", "plan.h", "kernels.h", "fusion.cpp", "fusion.h"],
+    "batch_tile": ["fused.hip", "fused.h", "device.h", "plan.h", "kernels.h", "fusion.cpp", "fusion.h", "abi.cpp"],
+    "sweep": ["sweep.hip", "device.h", "plan.h", "kernels.h", "planner.cpp", "planner.h"],
+    "block_mfma": ["mfma.hip", "device.h", "plan.h", "kernels.h", "planner.cpp", "planner.h"],
+}
+
+
+def source_digest(kernel: str) -> str:
+    fam = next((k for k in KERNEL_SOURCES if kernel.startswith(k)), None)
+    names = KERNEL_SOURCES[fam] if fam else sorted(os.listdir(os.path.join(ROOT, "paper_2410_17876_amd", "csrc")))
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2410_17876_amd", "csrc", "*"))):
-        h.update(open(f, "rb").read())
+    for name in names:
+        h.update(name.encode())
+        h.update(open(os.path.join(ROOT, "paper_2410_17876_amd", "csrc", name), "rb").read())
     return h.hexdigest()[:16]
 
 
 def load_traffic(kernel: str):
-    """Counter-measured bytes per launch for `kernel`, if taken on the current source."""
-    digest = source_digest()
+    """Counter-measured bytes per launch for `kernel`, if taken on its current sources."""
+    digest = source_digest(kernel)
     for f in glob.glob(os.path.join(ROOT, "profiles", "*traffic*.json")):
         try:
             d = json.load(open(f))
@@ -207,7 +220,31 @@ def run_mode(qd, st, dims, gates, precision, mode, steps, warmup):
     }
 
 
-def run_precision(qd, dims, gates, precision, upload, steps, warmup, modes):
+def lookahead_roundtrip(qd, st, dims, gates, precision, upload, values_at):
+    """The look-ahead path on the full register: the circuit, then its inverse
+    (each through qd_apply_circuit with the same look-ahead), must return the
+    input; max-abs and relative error on sampled amplitudes."""
+    import numpy as np
+
+    upload(st)
+    st.run_circuit(gates, reorder=LOOKAHEAD)
+    st.run_circuit([g.inverse() for g in reversed(gates)], reorder=LOOKAHEAD)
+    st.synchronize()
+    rng = np.random.default_rng(45)
+    idx = np.unique(np.concatenate([rng.integers(0, st.D, size=20000), [0, st.D - 1]]))
+    t = __import__("torch").as_tensor(idx, device=st.device)
+    v = st.buffer.view(-1, 2)[t].double().cpu().numpy()
+    got = v[:, 0] + 1j * v[:, 1]
+    want = values_at(idx)
+    if precision == "c64":
+        want = round32(want)
+    err = error_stats(got, want)
+    log(f"{precision}: look-ahead circuit + inverse on the full register: max-abs error {err['max_abs']:.3e} "
+        f"on {idx.size} sampled amplitudes")
+    return dict(err, samples=int(idx.size), gates=2 * len(gates))
+
+
+def run_precision(qd, dims, gates, precision, upload, steps, warmup, modes, values_at=None):
     import torch
 
     st = qd.State(dims, precision, init=None)
@@ -222,6 +259,8 @@ def run_precision(qd, dims, gates, precision, upload, steps, warmup, modes):
         st.synchronize()
         log(f"{precision}: state uploaded in {time.time() - t0:.1f} s")
         out[mode] = run_mode(qd, st, dims, gates, precision, mode, steps, warmup)
+    if "lookahead" in modes and values_at is not None:
+        out["lookahead"]["roundtrip"] = lookahead_roundtrip(qd, st, dims, gates, precision, upload, values_at)
     st.close()
     del st
     torch.cuda.empty_cache()
@@ -402,21 +441,180 @@ def run_sparse_ghz(qd, reps=3):
             "registers": out}
 
 
+def host_info() -> dict:
+    """CPU model, usable cores and RAM of the host the oracle runs on."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    ram = None
+    try:
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal:"):
+                ram = round(int(line.split()[1]) * 1024 / 2**30, 1)
+                break
+    except OSError:
+        pass
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    return {"cpu_model": model, "cores": cores, "ram_GiB": ram}
+
+
+def oracle_threads_all() -> int:
+    # the host's usable cores, capped at the 16 a one-GPU share of the box has
+    return max(1, min(16, host_info()["cores"]))
+
+
 def cpu_baseline(qd, dims, gates, psi, seconds):
+    """The FP64 oracle on the same circuit and state: one thread for about
+    `seconds`, then the same gates on every usable core (OpenMP over classes,
+    per-amplitude arithmetic unchanged)."""
     import oracle
 
-    done, updates = 0, 0
+    def leg(threads, max_gates=None):
+        done, updates = 0, 0
+        t0 = time.perf_counter()
+        with oracle.threads(threads):
+            for g in gates[:max_gates]:
+                oracle.apply_gate(dims, psi, g)
+                done += 1
+                updates += qd.gate_info(dims, g.targets, g.U, g.controls, g.values, "c128")["updated"]
+                if max_gates is None and time.perf_counter() - t0 >= seconds:
+                    break
+        return done, updates, time.perf_counter() - t0
+
+    n1, u1, t1 = leg(1)
+    nt = oracle_threads_all()
+    nn, un, tn = leg(nt, n1)
+    host = host_info()
+    return {"value": un / tn, "unit": "updates/s", "cores": nt, "kind": "oracle",
+            "sample": f"first {nn} of {len(gates)} gates on the full D={math.prod(dims)} state "
+                      f"(FP64 oracle, {nt} threads, {tn:.1f} s; one thread: {t1:.1f} s)",
+            "single_core": {"value": u1 / t1, "unit": "updates/s", "cores": 1, "gates": n1, "seconds": round(t1, 2)},
+            "all_cores": {"value": un / tn, "unit": "updates/s", "cores": nt, "gates": nn, "seconds": round(tn, 2)},
+            "host": host}
+
+
+def round32(v):
+    import numpy as np
+    return v.real.astype(np.float32).astype(np.float64) + 1j * v.imag.astype(np.float32).astype(np.float64)
+
+
+def error_stats(got, ref) -> dict:
+    import numpy as np
+    d = np.abs(got - ref)
+    mx = float(np.max(d))
+    return {"max_abs": mx, "rel_to_max_amp": mx / float(np.max(np.abs(ref))),
+            "rel_l2": float(np.linalg.norm(got - ref) / np.linalg.norm(ref))}
+
+
+def headline_error_vs_oracle(qd, gates_fn, lookahead):
+    """The headline path (qd_apply_circuit, fused passes, the same look-ahead and
+    default tiles) on the scaled-down register 2^10 x 3^6 x 4^2 with the same
+    500-gate mix and a Gaussian input, compared element by element with the FP64
+    oracle (the complex64 run against the oracle from the FP32-rounded input)."""
+    import numpy as np
+    import oracle
+    from qd_inputs import states
+
+    dims = [2] * 10 + [3] * 6 + [4] * 2
+    _, gates = gates_fn(dims)
+    D = math.prod(dims)
+    psi0 = states.GaussianState(D, seed=1001).full()
+    out = {"register": "2^10 x 3^6 x 4^2", "D": D, "gates": len(gates), "lookahead": lookahead}
     t0 = time.perf_counter()
-    for g in gates:
-        oracle.apply_gate(dims, psi, g)
-        done += 1
-        updates += qd.gate_info(dims, g.targets, g.U, g.controls, g.values, "c128")["updated"]
-        if time.perf_counter() - t0 >= seconds:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": updates / dt, "unit": "updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {done} of {len(gates)} gates on the full D={math.prod(dims)} state "
-                      f"(FP64 oracle, one thread, {dt:.1f} s)"}
+    for p in ("c128", "c64"):
+        inp = psi0 if p == "c128" else round32(psi0)
+        with oracle.threads(oracle_threads_all()):
+            ref = oracle.run(dims, gates, inp)
+        st = qd.State(dims, p, init=None).set_amplitudes(psi0)
+        st.run_circuit(gates, reorder=lookahead)
+        out[p] = error_stats(st.amplitudes(), ref)
+        st.close()
+    log(f"headline path vs oracle on {out['register']}: c128 max-abs {out['c128']['max_abs']:.3e}, "
+        f"c64 max-abs {out['c64']['max_abs']:.3e} ({time.perf_counter() - t0:.1f} s)")
+    return out
+
+
+def run_plain_small(qd, reps):
+    """The plain workload: dims [2,2,2,2,3,3] (D = 144), complex128, |0..0>, 200
+    gates of the basic mix (seed 1000). Launch-latency bound: one launch per
+    gate (qd_apply_gate) against the whole circuit in one fused launch
+    (qd_apply_circuit). Error vs the FP64 oracle on the whole state."""
+    import oracle
+    import torch
+    from qd_inputs import circuits
+
+    dims, gates = circuits.plain()
+    gl = qd.GateList(gates)
+    ref = oracle.run(dims, gates)
+    upd = sum(qd.gate_info(dims, g.targets, g.U, g.controls, g.values, "c128")["updated"] for g in gates)
+    out = {"workload": "dims [2,2,2,2,3,3] (D=144), complex128, |0..0>, 200 gates of the basic mix (seed 1000)",
+           "unit": "gates/s", "dtype": "f64"}
+    st = qd.State(dims, "c128")
+    forms = {"per_gate_launches": lambda: st.run(gates),
+             "one_launch": lambda: st.run_circuit(gl)}
+    for name, fn in forms.items():
+        st.reset(0)
+        info = fn()
+        err = error_stats(st.amplitudes(), ref)
+        for _ in range(max(1, reps // 10)):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        r = {"value": len(gates) * reps / dt, "unit": "gates/s", "updates_per_s": upd * reps / dt,
+             "us_per_circuit": 1e6 * dt / reps, "circuits": reps, "error_vs_oracle": err}
+        if name == "one_launch":
+            r["passes"] = info["passes"]
+            r["fused_passes"] = info["fused_passes"]
+        out[name] = r
+        log(f"plain D=144 {name}: {r['value']:.3e} gates/s ({r['us_per_circuit']:.1f} us per 200-gate circuit), "
+            f"max-abs error {err['max_abs']:.2e}")
+    out["value"] = out["one_launch"]["value"]
+    st.close()
+    return out
+
+
+def ququint_layer_errors(qd):
+    """The ququint gate mix (Haar gates on 2 or 3 of the qudits, 25 and 125
+    members) on 8 ququints (D = 390625, the largest the oracle advances in a few
+    seconds per layer), GPU and oracle in lockstep from |0..0>: the max-abs error
+    after each gate (a layer: the state is materialised after every gate on this
+    path), in complex64 and complex128."""
+    import numpy as np
+    import oracle
+    from qd_inputs import circuits
+
+    dims, gates = circuits.fused(dims=[5] * 8)
+    ref = oracle.zero_state(dims)
+    sts = {p: qd.State(dims, p) for p in ("c64", "c128")}
+    errs = {p: [] for p in sts}
+    t0 = time.perf_counter()
+    with oracle.threads(oracle_threads_all()):
+        for g in gates:
+            oracle.apply_gate(dims, ref, g)
+            for p, st in sts.items():
+                st.apply_gate(g)
+                errs[p].append(float(np.max(np.abs(st.amplitudes() - ref))))
+    for st in sts.values():
+        st.close()
+    log(f"ququint 5^8 lockstep, {len(gates)} layers in {time.perf_counter() - t0:.1f} s: max-abs error "
+        f"c64 {max(errs['c64']):.2e}, c128 {max(errs['c128']):.2e}")
+    return {"register": "5^8 (D=390625)", "gates": len(gates), "seed": circuits.SEEDS["fused"],
+            "layer": "one gate (the GPU materialises the state after every gate)",
+            "c64_max_abs": max(errs["c64"]), "c128_max_abs": max(errs["c128"]),
+            "c64_per_layer": [float(f"{e:.3g}") for e in errs["c64"]],
+            "c128_per_layer": [float(f"{e:.3g}") for e in errs["c128"]]}
 
 
 def main() -> int:
@@ -444,6 +642,10 @@ def main() -> int:
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "tune_cache.json"),
                     help="autotuner cache file")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-error", action="store_true",
+                    help="skip the error checks against the oracle (headline path on 2^10 x 3^6 x 4^2, ququint layers)")
+    ap.add_argument("--no-plain-small", action="store_true", help="skip the D=144 launch-latency workload")
+    ap.add_argument("--plain-small-reps", type=int, default=2000, help="circuits timed per form on D=144")
     ap.add_argument("--small", action="store_true", help="2^10 x 3^6 x 4^2 register (quick check)")
     ap.add_argument("--tile-c128", type=int, default=0, help="fused tile size, c128 (0 = library default)")
     ap.add_argument("--tile-c64", type=int, default=0, help="fused tile size, c64 (0 = library default)")
@@ -490,9 +692,15 @@ def main() -> int:
         else:
             G.fill(lambda start, vals: st.set_interleaved(vals, start))
 
-    res = {"c128": run_precision(qd, dims, gates, "c128", upload, args.steps, args.warmup, modes)}
+    values_at = (lambda idx: host[idx]) if host is not None else G.values
+    res = {"c128": run_precision(qd, dims, gates, "c128", upload, args.steps, args.warmup, modes, values_at)}
     if not args.no_c64:
-        res["c64"] = run_precision(qd, dims, gates, "c64", upload, args.steps, args.warmup, modes)
+        res["c64"] = run_precision(qd, dims, gates, "c64", upload, args.steps, args.warmup, modes, values_at)
+    if not args.no_error:
+        res["error"] = headline_error_vs_oracle(qd, lambda d: circuits.large(n_gates=args.gates, dims=d),
+                                                LOOKAHEAD)
+    if not args.no_plain_small:
+        res["plain_small"] = run_plain_small(qd, args.plain_small_reps)
     if not args.no_ququint:
         qdims, qgates = circuits.fused()
         qst = qd.State(qdims, "c64")
@@ -506,6 +714,8 @@ def main() -> int:
         qst.close()
         del qst
         torch.cuda.empty_cache()
+        if not args.no_error:
+            res["ququint_layers"] = ququint_layer_errors(qd)
     if not args.no_batched:
         for p in (["c64", "c128"] if not args.no_c64 else ["c128"]):
             res[f"batched_{p}"] = run_batched(qd, p, args.steps, args.warmup, args.tune_cache, args.lookahead)
@@ -543,6 +753,7 @@ def main() -> int:
                    "lookahead": LOOKAHEAD if head_mode == "lookahead" else 0},
         "roofline": h["roofline"],
         "cpu_baseline": cpu,
+        "error_vs_oracle": dict(res["error"], full_register_roundtrip=h.get("roundtrip")) if "error" in res else None,
         "copy_ceiling_GBps": {p: res[p]["copy_ceiling_GBps"] for p in ("c128", "c64") if p in res},
         "norm_last_step": h["norm_last_step"],
         "launches_per_step": h["launches_per_step"],
@@ -556,6 +767,8 @@ def main() -> int:
             "value": r["value"], "unit": "updates/s", "dtype": "f32", "ms_per_step": r["ms_per_step"],
             "launches_per_step": r["launches_per_step"], "roofline": r["roofline"],
             "norm_last_step": r["norm_last_step"], "kernels": r["kernels"]}
+        if "ququint_layers" in res:
+            line["runs"]["ququint_mfma_c64"]["error_per_layer"] = res["ququint_layers"]
     if "ququint_c128" in res:
         r = res["ququint_c128"]
         line["runs"]["ququint_mfma_c128"] = {
@@ -563,6 +776,8 @@ def main() -> int:
             "value": r["value"], "unit": "updates/s", "dtype": "f64", "ms_per_step": r["ms_per_step"],
             "launches_per_step": r["launches_per_step"], "roofline": r["roofline"],
             "norm_last_step": r["norm_last_step"], "kernels": r["kernels"]}
+    if "plain_small" in res:
+        line["runs"]["plain_d144_c128"] = res["plain_small"]
     if "sparse" in res:
         line["runs"]["sparse_ghz_c128"] = res["sparse"]
     if "served" in res:
@@ -579,7 +794,7 @@ def main() -> int:
             if p == "c128" and m == head_mode:
                 continue
             r = res[p][m]
-            line["runs"][f"{m}_{p}"] = {"value": r["value"], "unit": "updates/s",
+            line["runs"][f"{m}_{p}"] = {"value": r["value"], "unit": "updates/s", "roundtrip": r.get("roundtrip"),
                                         "dtype": "f64" if p == "c128" else "f32",
                                         "ms_per_step": r["ms_per_step"], "launches_per_step": r["launches_per_step"],
                                         "roofline": r["roofline"], "norm_last_step": r["norm_last_step"],

@@ -40,11 +40,39 @@ def lib():
         L.oracle_rows.argtypes = [C.c_int, f64p, C.c_int64, f64p, i32p, f64p]
         L.oracle_norm.argtypes = [C.c_int64, f64p, C.POINTER(C.c_double)]
         L.oracle_probabilities.argtypes = [C.c_int64, f64p, f64p]
+        L.oracle_set_threads.argtypes = [C.c_int]
+        L.oracle_get_threads.argtypes = []
         for f in (L.oracle_init_zero, L.oracle_apply, L.oracle_apply_masked, L.oracle_class_members, L.oracle_rows,
-                  L.oracle_norm, L.oracle_probabilities):
+                  L.oracle_norm, L.oracle_probabilities, L.oracle_set_threads, L.oracle_get_threads):
             f.restype = C.c_int
         _lib = L
     return _lib
+
+
+def set_threads(n: int) -> None:
+    """Threads for the per-gate scans (the result is bitwise the same for any count)."""
+    if lib().oracle_set_threads(int(n)) != 0:
+        raise ValueError("thread count must be >= 1")
+
+
+def get_threads() -> int:
+    return int(lib().oracle_get_threads())
+
+
+class threads:
+    """Context manager: run the enclosed oracle calls on n threads."""
+
+    def __init__(self, n: int):
+        self.n = int(n)
+
+    def __enter__(self):
+        self.prev = get_threads()
+        set_threads(self.n)
+        return self
+
+    def __exit__(self, *exc):
+        set_threads(self.prev)
+        return False
 
 
 def _i32(x) -> np.ndarray:

@@ -51,6 +51,33 @@ def rand_dims(rng, n_max=5, D_max=2000):
             return dims
 
 
+@pytest.fixture(autouse=True, params=[1, 4], ids=["1thread", "4threads"])
+def oracle_threads(request):
+    """Every pin runs with the oracle's scan on one thread and on four."""
+    with oracle.threads(request.param):
+        yield request.param
+
+
+def test_thread_split_is_bitwise():
+    # The scan over base indices may run on several threads: classes are
+    # disjoint (Sec. 2.3), so every amplitude gets the same operations in the
+    # same order and the result must not change by a single bit.
+    rng = np.random.default_rng(77)
+    dims = [2, 3, 5, 2, 4, 7, 3, 2, 2, 3]
+    psi0 = rand_state(rng, math.prod(dims))
+    gates = [rand_gate(rng, dims, m_max=3) for _ in range(40)]
+    masked = [(g.targets, g.U, g.controls, [(1 << dims[c]) - 1 - (1 << v) for c, v in zip(g.controls, g.values)])
+              for g in gates[:10]]
+    out = []
+    for n in (1, 2, 7):
+        with oracle.threads(n):
+            psi = oracle.run(dims, gates, psi0)
+            for t, U, c, mk in masked:
+                oracle.apply_masked(dims, psi, t, U, c, mk)
+            out.append(psi)
+    assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
+
+
 # --- worked example (Sec. 2.5) -------------------------------------------------
 
 def load_worked_example():
