@@ -70,6 +70,7 @@ enum qd_location { QD_DEVICE = 0, QD_HOST = 1 };
 #define QD_MAX_TARGETS 3
 #define QD_MAX_M 343
 #define QD_MAX_CONTROLS 24
+#define QD_SPARSE_MAX_QUDITS 126
 
 /* ---- host-only calls (no device needed) ---------------------------------- */
 
@@ -234,27 +235,55 @@ int qd_circuit_plan(const int32_t* dims, int32_t n, int32_t precision, const qd_
  * (basis index, complex128 amplitude) pairs in device memory sorted by index.
  * A gate groups the entries by class (Sec. 2.3), applies U to every class that
  * has a nonzero member (absent members are 0), keeps the nonzero results and
- * leaves entries whose controls do not hold (Sec. 2.4) unchanged. Calls are
- * synchronous and use the device that was current at creation. */
+ * leaves entries whose controls do not hold (Sec. 2.4) unchanged. The paper's
+ * sparse registers stop at a signed 64-bit index (Sec. 3) and it names wider
+ * integer keys as the way on (Sec. 4): here a basis index is a key of up to
+ * three 64-bit words, so a sparse register may have up to QD_SPARSE_MAX_QUDITS
+ * qudits and any D < 2^127 (e.g. 126 qubits, 80 qutrits, 63 ququads, 54
+ * ququints). Gates are enqueued on the state's stream (the null stream unless
+ * qd_sparse_set_stream); qd_sparse_nnz and the get calls wait for it and report
+ * device errors. Use one thread per state; the device is the one current at
+ * creation. */
 typedef struct qd_sparse qd_sparse;
 
-/* |0...0> on the register (validation as qd_dim). */
+/* Host-only: D = prod dims of a sparse register as a 128-bit value (*D_lo, *D_hi),
+ * and the number of 64-bit words of its keys (*words, 1..3). QD_ERR_INVALID_ARGUMENT
+ * for n outside 1..QD_SPARSE_MAX_QUDITS, a null dims or a dim outside 2..7;
+ * QD_ERR_DIM_OVERFLOW when D >= 2^127. Output pointers may be null. */
+int qd_sparse_dim(const int32_t* dims, int32_t n, uint64_t* D_lo, uint64_t* D_hi, int32_t* words);
+
+/* |0...0> on the register (validation as qd_sparse_dim). Synchronous. */
 int qd_sparse_create(const int32_t* dims, int32_t n, qd_sparse** out);
+
+/* Wait for the state's stream, then free the state. */
 int qd_sparse_destroy(qd_sparse* s);
 
-/* Apply U (M x M, row-major [out][in], interleaved FP64) to targets[0..k-1],
- * controlled on controls[l] holding values[l]. Validation as qd_check_gate;
- * M at most 16 and (stored entries) x M below 2^31 (else QD_ERR_NOT_SUPPORTED).
- * On an error the state is unchanged. */
+/* Run the state's work on hip_stream (null = default stream); work queued on
+ * the previous stream is waited for first. */
+int qd_sparse_set_stream(qd_sparse* s, void* hip_stream);
+
+/* Apply U (M x M, row-major [out][in], interleaved FP64, copied before the call
+ * returns) to targets[0..k-1], controlled on controls[l] holding values[l].
+ * Validation as qd_check_gate (on the sparse register); M at most 16 and
+ * (stored entries) x M below 2^31 (else QD_ERR_NOT_SUPPORTED). On an error the
+ * state is unchanged. Asynchronous: while (stored entries) x M stays within 1024
+ * the gate is one kernel launch and reads nothing back; larger gates read the
+ * result count back once. */
 int qd_sparse_apply_gate(qd_sparse* s, const int32_t* targets, int32_t k, const int32_t* controls,
                          const int32_t* values, int32_t m, const double* U);
 
-/* Number of stored (nonzero) amplitudes. */
-int qd_sparse_nnz(const qd_sparse* s, uint64_t* nnz);
+/* Number of stored (nonzero) amplitudes. Waits for the state's stream. */
+int qd_sparse_nnz(qd_sparse* s, uint64_t* nnz);
 
 /* Copy the first min(cap, nnz) entries, in increasing basis index, to host
- * arrays keys[cap] and amps[2 * cap] (interleaved re, im). */
-int qd_sparse_get(const qd_sparse* s, uint64_t* keys, double* amps, uint64_t cap);
+ * arrays keys[cap] and amps[2 * cap] (interleaved re, im). For registers with
+ * D < 2^64 only (else QD_ERR_NOT_SUPPORTED: use qd_sparse_get_wide). Waits for
+ * the state's stream. */
+int qd_sparse_get(qd_sparse* s, uint64_t* keys, double* amps, uint64_t cap);
+
+/* As qd_sparse_get for any register: keys[2 * cap] receives each basis index as
+ * two 64-bit halves (low, high) of its 128-bit value. */
+int qd_sparse_get_wide(qd_sparse* s, uint64_t* keys, double* amps, uint64_t cap);
 
 /* ---- batches of independent states ---------------------------------------------- */
 

@@ -74,11 +74,14 @@ def _load() -> C.CDLL:
         "qd_state_info": [vp, u64p, i32p, C.POINTER(vp)],
         "qd_apply_gate": [vp, i32p, C.c_int32, i32p, i32p, C.c_int32, f64p],
         "qd_apply_gate_masked": [vp, i32p, C.c_int32, i32p, C.POINTER(C.c_uint32), C.c_int32, f64p],
+        "qd_sparse_dim": [i32p, C.c_int32, u64p, u64p, i32p],
         "qd_sparse_create": [i32p, C.c_int32, C.POINTER(vp)],
         "qd_sparse_destroy": [vp],
+        "qd_sparse_set_stream": [vp, vp],
         "qd_sparse_apply_gate": [vp, i32p, C.c_int32, i32p, i32p, C.c_int32, f64p],
         "qd_sparse_nnz": [vp, u64p],
         "qd_sparse_get": [vp, u64p, f64p, C.c_uint64],
+        "qd_sparse_get_wide": [vp, u64p, f64p, C.c_uint64],
         "qd_norm": [vp, f64p],
         "qd_probabilities": [vp, f64p, C.c_uint64, C.c_int32],
         "qd_synchronize": [vp],
@@ -370,14 +373,29 @@ def _batch_args(states, gate_lists):
     return gls, hs, gp, counts
 
 
-class SparseState:
-    """A sparse statevector (qd_sparse_*): nonzero amplitudes as (basis index, complex128) pairs on the GPU."""
+def sparse_dim(dims) -> tuple:
+    """(D, key words) of a sparse register: D = prod dims as a Python int (< 2^127)."""
+    d, dp = _i32(dims)
+    lo, hi, w = C.c_uint64(), C.c_uint64(), C.c_int32()
+    check(lib.qd_sparse_dim(dp, len(dims), C.byref(lo), C.byref(hi), C.byref(w)))
+    return (hi.value << 64) | lo.value, w.value
 
-    def __init__(self, dims):
+
+class SparseState:
+    """A sparse statevector (qd_sparse_*): nonzero amplitudes as (basis index, complex128) pairs on the GPU.
+
+    Gates run on the torch stream current at creation (or the one given)."""
+
+    def __init__(self, dims, stream=None):
+        import torch
+
         self.dims = [int(d) for d in dims]
+        self.D, self.words = sparse_dim(self.dims)
         d, dp = _i32(self.dims)
         self._h = C.c_void_p()
         check(lib.qd_sparse_create(dp, len(self.dims), C.byref(self._h)))
+        st = stream if stream is not None else torch.cuda.current_stream()
+        check(lib.qd_sparse_set_stream(self._h, C.c_void_p(st.cuda_stream)))
 
     def apply(self, targets, U, controls=(), values=()) -> "SparseState":
         t, tp = _i32(targets)
@@ -396,13 +414,20 @@ class SparseState:
         return out.value
 
     def entries(self):
-        """(keys uint64, amplitudes complex128), in increasing basis index."""
+        """(keys, amplitudes complex128) in increasing basis index: keys is a uint64
+        array when D < 2^64, else a list of Python ints."""
         n = self.nnz()
-        keys = np.zeros(max(1, n), dtype=np.uint64)
         amps = np.zeros(2 * max(1, n), dtype=np.float64)
-        check(lib.qd_sparse_get(self._h, keys.ctypes.data_as(C.POINTER(C.c_uint64)),
-                                amps.ctypes.data_as(C.POINTER(C.c_double)), n))
-        return keys[:n], amps.view(np.complex128)[:n]
+        if self.D < 2**64:
+            keys = np.zeros(max(1, n), dtype=np.uint64)
+            check(lib.qd_sparse_get(self._h, keys.ctypes.data_as(C.POINTER(C.c_uint64)),
+                                    amps.ctypes.data_as(C.POINTER(C.c_double)), n))
+            return keys[:n], amps.view(np.complex128)[:n]
+        halves = np.zeros(2 * max(1, n), dtype=np.uint64)
+        check(lib.qd_sparse_get_wide(self._h, halves.ctypes.data_as(C.POINTER(C.c_uint64)),
+                                     amps.ctypes.data_as(C.POINTER(C.c_double)), n))
+        keys = [(int(halves[2 * i + 1]) << 64) | int(halves[2 * i]) for i in range(n)]
+        return keys, amps.view(np.complex128)[:n]
 
     def close(self) -> None:
         if self._h:

@@ -434,33 +434,93 @@ int qd_apply_gate(qd_state* s, const int32_t* targets, int32_t k, const int32_t*
 
 struct qd_sparse {
     int n = 0;
-    int32_t dims[QD_MAX_QUDITS] = {};
-    uint64_t s[QD_MAX_QUDITS] = {};
+    int32_t dims[QD_SPARSE_MAX_QUDITS] = {};
+    int word[QD_SPARSE_MAX_QUDITS] = {};        // key word of each qudit
+    uint64_t stride[QD_SPARSE_MAX_QUDITS] = {}; // stride inside that word
+    uint64_t P[qd::kKeyWords] = {1, 1, 1};      // product of each word's dims
+    uint64_t D_lo = 0, D_hi = 0;
     int device = 0;
     qd::SparseData d;
 };
+
+namespace {
+
+int sparse_device(const qd_sparse* s) {
+    int cur = -1;
+    QD_HIP(hipGetDevice(&cur), "hipGetDevice");
+    if (cur != s->device) QD_HIP(hipSetDevice(s->device), "hipSetDevice");
+    return QD_OK;
+}
+
+int sparse_hip_err(hipError_t e, const char* what) {
+    if (e == hipErrorIllegalState)
+        return set_err(QD_ERR_DEVICE, std::string(what) + ": a gate found more stored entries than planned");
+    return hip_err(e, what);
+}
+
+// The first c entries as 128-bit basis indices (lo, hi per entry, or only lo
+// when hi is null) and amplitudes.
+int sparse_fetch(qd_sparse* s, uint64_t cap, uint64_t* lo, uint64_t* hi, double* amps) {
+    int rc = sparse_device(s);
+    if (rc) return rc;
+    uint64_t nnz = 0;
+    hipError_t e = qd::sparse_count(s->d, &nnz);
+    if (e != hipSuccess) return sparse_hip_err(e, "sparse get");
+    const uint64_t c = std::min<uint64_t>(cap, nnz);
+    if (c == 0) return QD_OK;
+    const int W = s->d.W;
+    const uint64_t scap = s->d.slot_cap[s->d.cur];
+    std::vector<uint64_t> words((size_t)W * c);
+    void* slot = s->d.slot[s->d.cur];
+    for (int w = 0; w < W; ++w)
+        QD_HIP(hipMemcpy(words.data() + (size_t)w * c, qd::slot_keys(slot) + (size_t)w * scap, c * 8,
+                         hipMemcpyDeviceToHost),
+               "sparse get keys");
+    QD_HIP(hipMemcpy(amps, qd::slot_amps(slot, W, scap), c * 16, hipMemcpyDeviceToHost), "sparse get amplitudes");
+    // basis index = w_0 + P_0 (w_1 + P_1 w_2)
+    for (uint64_t i = 0; i < c; ++i) {
+        unsigned __int128 v = 0;
+        for (int w = W - 1; w >= 0; --w) v = v * s->P[w] + words[(size_t)w * c + i];
+        if (hi) {
+            lo[2 * i] = (uint64_t)v;
+            lo[2 * i + 1] = (uint64_t)(v >> 64);
+        } else {
+            lo[i] = (uint64_t)v;
+        }
+    }
+    return QD_OK;
+}
+
+}  // namespace
+
+int qd_sparse_dim(const int32_t* dims, int32_t n, uint64_t* D_lo, uint64_t* D_hi, int32_t* words) {
+    std::string err;
+    int W = 0;
+    int rc = sparse_layout(dims, n, nullptr, nullptr, &W, nullptr, D_lo, D_hi, &err);
+    if (rc) return set_err(rc, err);
+    if (words) *words = W;
+    return QD_OK;
+}
 
 int qd_sparse_create(const int32_t* dims, int32_t n, qd_sparse** out) {
     if (!out) return set_err(QD_ERR_INVALID_ARGUMENT, "out is null");
     *out = nullptr;
     std::string err;
-    uint64_t D = 0;
-    int rc = check_dims(dims, n, &D, &err);
-    if (rc) return set_err(rc, err);
     qd_sparse* s = new qd_sparse;
-    s->n = n;
-    uint64_t st = 1;
-    for (int i = 0; i < n; ++i) {
-        s->dims[i] = dims[i];
-        s->s[i] = st;
-        st *= (uint64_t)dims[i];
+    int W = 0;
+    int rc = sparse_layout(dims, n, s->word, s->stride, &W, s->P, &s->D_lo, &s->D_hi, &err);
+    if (rc) {
+        delete s;
+        return set_err(rc, err);
     }
+    s->n = n;
+    for (int i = 0; i < n; ++i) s->dims[i] = dims[i];
     hipError_t e = hipGetDevice(&s->device);
-    if (e == hipSuccess) e = qd::sparse_init(s->d);
+    if (e == hipSuccess) e = qd::sparse_init(s->d, W);
     if (e != hipSuccess) {
         qd::sparse_release(s->d);
         delete s;
-        return set_err(QD_ERR_DEVICE, std::string("sparse state: ") + hipGetErrorString(e));
+        return hip_err(e, "sparse state");
     }
     *out = s;
     return QD_OK;
@@ -474,61 +534,86 @@ int qd_sparse_destroy(qd_sparse* s) {
     return QD_OK;
 }
 
+int qd_sparse_set_stream(qd_sparse* s, void* hip_stream) {
+    if (!s) return set_err(QD_ERR_INVALID_ARGUMENT, "state is null");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    if (st == s->d.stream) return QD_OK;
+    int rc = sparse_device(s);
+    if (rc) return rc;
+    QD_HIP(hipStreamSynchronize(s->d.stream), "synchronizing the previous stream");
+    s->d.stream = st;
+    return QD_OK;
+}
+
 int qd_sparse_apply_gate(qd_sparse* s, const int32_t* targets, int32_t k, const int32_t* controls,
                          const int32_t* values, int32_t m, const double* U) {
     if (!s) return set_err(QD_ERR_INVALID_ARGUMENT, "state is null");
     std::string err;
-    int rc = check_gate(s->dims, s->n, targets, k, controls, values, m, &err);
+    int rc = check_gate_shape(s->dims, s->n, targets, k, controls, values, m, &err);
     if (rc) return set_err(rc, err);
     if (!U) return set_err(QD_ERR_INVALID_ARGUMENT, "U is null");
     qd::SparseGate g;
     std::memset(&g, 0, sizeof g);
+    g.W = s->d.W;
     g.k = k;
     g.M = 1;
     for (int l = 0; l < k; ++l) {
-        g.ts[l] = s->s[targets[l]];
+        g.tw[l] = s->word[targets[l]];
+        g.ts[l] = s->stride[targets[l]];
         g.td[l] = (uint32_t)s->dims[targets[l]];
         g.M *= s->dims[targets[l]];
     }
     if (g.M > qd::kSparseMaxM) return set_err(QD_ERR_NOT_SUPPORTED, "sparse gates act on at most 16 amplitudes");
-    if (s->d.nnz > (uint64_t)INT32_MAX / (uint64_t)g.M)
-        return set_err(QD_ERR_NOT_SUPPORTED, "sparse state too large: stored entries x class size must stay below 2^31");
     g.m = m;
     for (int l = 0; l < m; ++l) {
-        g.cs[l] = s->s[controls[l]];
+        g.cw[l] = s->word[controls[l]];
+        g.cs[l] = s->stride[controls[l]];
         g.cd[l] = (uint32_t)s->dims[controls[l]];
         g.cv[l] = (uint32_t)values[l];
     }
     for (int a = 0; a < g.M; ++a) {
-        uint64_t off = 0;
         int r = a;
         for (int l = 0; l < k; ++l) {
-            off += (uint64_t)(r % (int)g.td[l]) * g.ts[l];
+            g.off[a][g.tw[l]] += (uint64_t)(r % (int)g.td[l]) * g.ts[l];
             r /= (int)g.td[l];
         }
-        g.off[a] = off;
     }
-    hipError_t e = hipSetDevice(s->device);
-    if (e == hipSuccess) e = qd::sparse_apply(s->d, g, U);
-    if (e != hipSuccess) return set_err(QD_ERR_DEVICE, std::string("sparse gate: ") + hipGetErrorString(e));
+    // Every column with at most one nonzero: each entry feeds at most one result,
+    // so the gate cannot raise the entry count.
+    bool cols_single = true;
+    for (int a = 0; a < g.M && cols_single; ++a) {
+        int nz = 0;
+        for (int r = 0; r < g.M; ++r) nz += (U[2 * (r * g.M + a)] != 0.0 || U[2 * (r * g.M + a) + 1] != 0.0);
+        cols_single = nz <= 1;
+    }
+    rc = sparse_device(s);
+    if (rc) return rc;
+    hipError_t e = qd::sparse_apply(s->d, g, U, cols_single);
+    if (e == hipErrorNotSupported)
+        return set_err(QD_ERR_NOT_SUPPORTED, "sparse state too large: stored entries x class size must stay below 2^31");
+    if (e != hipSuccess) return sparse_hip_err(e, "sparse gate");
     return QD_OK;
 }
 
-int qd_sparse_nnz(const qd_sparse* s, uint64_t* nnz) {
+int qd_sparse_nnz(qd_sparse* s, uint64_t* nnz) {
     if (!s || !nnz) return set_err(QD_ERR_INVALID_ARGUMENT, "null argument");
-    *nnz = s->d.nnz;
+    int rc = sparse_device(s);
+    if (rc) return rc;
+    hipError_t e = qd::sparse_count(s->d, nnz);
+    if (e != hipSuccess) return sparse_hip_err(e, "sparse count");
     return QD_OK;
 }
 
-int qd_sparse_get(const qd_sparse* s, uint64_t* keys, double* amps, uint64_t cap) {
+int qd_sparse_get(qd_sparse* s, uint64_t* keys, double* amps, uint64_t cap) {
     if (!s || (cap && (!keys || !amps))) return set_err(QD_ERR_INVALID_ARGUMENT, "null argument");
-    const uint64_t c = std::min<uint64_t>(cap, s->d.nnz);
-    if (c == 0) return QD_OK;
-    hipError_t e = hipSetDevice(s->device);
-    if (e == hipSuccess) e = hipMemcpy(keys, s->d.keys, c * 8, hipMemcpyDeviceToHost);
-    if (e == hipSuccess) e = hipMemcpy(amps, s->d.amps, c * 16, hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return set_err(QD_ERR_DEVICE, std::string("sparse get: ") + hipGetErrorString(e));
-    return QD_OK;
+    if (s->D_hi) return set_err(QD_ERR_NOT_SUPPORTED, "register has D >= 2^64: use qd_sparse_get_wide");
+    return sparse_fetch(s, cap, keys, nullptr, amps);
+}
+
+int qd_sparse_get_wide(qd_sparse* s, uint64_t* keys, double* amps, uint64_t cap) {
+    if (!s || (cap && (!keys || !amps))) return set_err(QD_ERR_INVALID_ARGUMENT, "null argument");
+    uint64_t dummy = 0;
+    return sparse_fetch(s, cap, keys, &dummy, amps);
 }
 
 static constexpr uint64_t kMaxMaskedCombos = 4096;

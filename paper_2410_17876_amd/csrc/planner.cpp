@@ -71,15 +71,50 @@ int check_dims(const int32_t* dims, int32_t n, uint64_t* D, std::string* err) {
     return QD_OK;
 }
 
-int check_gate(const int32_t* dims, int32_t n, const int32_t* targets, int32_t k, const int32_t* controls,
-               const int32_t* values, int32_t m, std::string* err) {
-    int rc = check_dims(dims, n, nullptr, err);
-    if (rc) return rc;
+int sparse_layout(const int32_t* dims, int32_t n, int* word, uint64_t* stride, int* W, uint64_t* P, uint64_t* D_lo,
+                  uint64_t* D_hi, std::string* err) {
+    if (!dims) return fail(err, QD_ERR_INVALID_ARGUMENT, "dims is null");
+    if (n < 1 || n > QD_SPARSE_MAX_QUDITS)
+        return fail(err, QD_ERR_INVALID_ARGUMENT, "n = %d qudits outside 1..%d", n, QD_SPARSE_MAX_QUDITS);
+    unsigned __int128 D = 1;
+    const unsigned __int128 limit = (unsigned __int128)1 << 127;
+    int w = 0;
+    uint64_t pw = 1;  // product of the dims packed into word w so far
+    for (int i = 0; i < n; ++i) {
+        if (dims[i] < QD_MIN_DIM || dims[i] > QD_MAX_DIM)
+            return fail(err, QD_ERR_INVALID_ARGUMENT, "dims[%d] = %d outside %d..%d", i, dims[i], QD_MIN_DIM,
+                        QD_MAX_DIM);
+        if (D > (limit - 1) / (unsigned)dims[i])
+            return fail(err, QD_ERR_DIM_OVERFLOW, "D = prod dims is not below 2^127");
+        D *= (unsigned)dims[i];
+        // A word takes qudits while the product of their dims stays below 2^64.
+        // A full word holds more than 2^64 / 7, so D < 2^127 needs at most 3.
+        if (pw > UINT64_MAX / (uint64_t)dims[i]) {
+            if (P) P[w] = pw;
+            if (++w >= kSparseKeyWords) return fail(err, QD_ERR_DIM_OVERFLOW, "register needs more than 3 key words");
+            pw = 1;
+        }
+        if (word) word[i] = w;
+        if (stride) stride[i] = pw;
+        pw *= (uint64_t)dims[i];
+    }
+    if (P) {
+        P[w] = pw;
+        for (int j = w + 1; j < kSparseKeyWords; ++j) P[j] = 1;
+    }
+    if (W) *W = w + 1;
+    if (D_lo) *D_lo = (uint64_t)D;
+    if (D_hi) *D_hi = (uint64_t)(D >> 64);
+    return QD_OK;
+}
+
+int check_gate_shape(const int32_t* dims, int32_t n, const int32_t* targets, int32_t k, const int32_t* controls,
+                     const int32_t* values, int32_t m, std::string* err) {
     if (k < 1) return fail(err, QD_ERR_INVALID_ARGUMENT, "a gate needs at least one target (k = %d)", k);
     if (!targets) return fail(err, QD_ERR_INVALID_ARGUMENT, "targets is null");
     if (m < 0) return fail(err, QD_ERR_INVALID_ARGUMENT, "negative control count %d", m);
     if (m > 0 && (!controls || !values)) return fail(err, QD_ERR_INVALID_ARGUMENT, "controls or values is null");
-    bool used[QD_MAX_QUDITS] = {false};
+    bool used[QD_SPARSE_MAX_QUDITS] = {false};
     for (int l = 0; l < k; ++l) {
         const int t = targets[l];
         if (t < 0 || t >= n) return fail(err, QD_ERR_INVALID_ARGUMENT, "target %d outside 0..%d", t, n - 1);
@@ -100,6 +135,13 @@ int check_gate(const int32_t* dims, int32_t n, const int32_t* targets, int32_t k
     if (m > QD_MAX_CONTROLS)
         return fail(err, QD_ERR_NOT_SUPPORTED, "%d controls; at most %d are supported", m, QD_MAX_CONTROLS);
     return QD_OK;
+}
+
+int check_gate(const int32_t* dims, int32_t n, const int32_t* targets, int32_t k, const int32_t* controls,
+               const int32_t* values, int32_t m, std::string* err) {
+    int rc = check_dims(dims, n, nullptr, err);
+    if (rc) return rc;
+    return check_gate_shape(dims, n, targets, k, controls, values, m, err);
 }
 
 static bool is_zero(const double* U, int i) { return U[2 * i] == 0.0 && U[2 * i + 1] == 0.0; }

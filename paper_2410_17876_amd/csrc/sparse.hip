@@ -1,20 +1,32 @@
 // sparse.hip - a gate on a sparse statevector (sparse.h).
 //
-// 1. classify: for every entry, its class base (the key with the target digits
-//    set to 0) and local index when the controls hold (Sec. 2.3, 2.4); an entry
-//    whose controls fail is its own one-member group (local index -1). A
-//    control-failing key never equals the base of a class whose controls hold
-//    (they differ in a control digit), so groups never mix the two.
-// 2. radix-sort the entries by group key (hipCUB).
-// 3. one thread per group head: gather the class's present members (missing
-//    ones are 0), y = U x, write the M results with their keys, flag the
-//    nonzero ones (a control-failing entry is copied unchanged).
-// 4. keep the flagged results and sort them by key.
+// Per gate (Sec. 2.3, 2.4):
+// 1. classify: every entry's group is its class base (the key with the target
+//    digits set to 0) and its local index, when the controls hold; an entry
+//    whose controls fail is its own group (local index -1), and such a key never
+//    equals the base of a class whose controls hold (they differ in a control
+//    digit), so the two kinds of groups never mix.
+// 2. one result per class with a present member: gather the members (absent
+//    ones are 0 and skipped), y = U x with textbook complex products summed in
+//    ascending column order, keep the nonzero results; a control-failing entry
+//    is kept unchanged.
+// 3. the kept results sorted by key become the new entries.
+//
+// Two forms. While (entries x class size) fits kSparseSmallCap, one workgroup
+// does all three steps in LDS (grouping by pairwise key comparison, ordering by
+// rank counting) and reads the entry count from, and writes it to, device
+// memory, so gates are enqueued back to back with no host synchronisation and
+// the matrix is read straight from pinned host memory. Beyond that, entries are
+// grouped with a radix sort by group key, one thread per group head computes
+// its class, and the kept results are radix-sorted by key (hipCUB; keys of
+// several words are sorted word by word, least significant word first, which a
+// stable radix sort makes lexicographic); the kept count is read back once.
 #include <hip/hip_runtime.h>
 
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
+#include <cstring>
 
 #include "sparse.h"
 
@@ -22,86 +34,223 @@ namespace qd {
 
 namespace {
 
-__global__ void sparse_classify(const uint64_t* __restrict__ keys, uint64_t n, const SparseGate g,
-                                uint64_t* __restrict__ group, int32_t* __restrict__ local,
-                                uint32_t* __restrict__ idx) {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint64_t key = keys[i];
-    bool hold = true;
+constexpr int kSmallThreads = 512;
+constexpr uint32_t kSmallIn = kSparseSmallCap / 2;  // entries of a small gate (class size >= 2)
+constexpr int kErrWord = 2;                         // nnz_dev[2]: set if a small gate saw more entries than planned
+
+__device__ __forceinline__ uint32_t digit_of(uint64_t v, uint64_t s, uint32_t d) { return (uint32_t)((v / s) % d); }
+
+// Group of one entry: returns its local index (the key becomes the class base)
+// when every control holds, else -1 (the key is left as it is).
+__device__ __forceinline__ int classify(const SparseGate& g, uint64_t (&key)[kKeyWords]) {
     for (int l = 0; l < g.m; ++l)
-        if ((key / g.cs[l]) % g.cd[l] != g.cv[l]) hold = false;
-    if (hold) {
-        int a = 0, w = 1;
-        uint64_t base = key;
-        for (int l = 0; l < g.k; ++l) {
-            const uint64_t dg = (key / g.ts[l]) % g.td[l];
-            a += (int)dg * w;
-            w *= (int)g.td[l];
-            base -= dg * g.ts[l];
-        }
-        group[i] = base;
-        local[i] = a;
-    } else {
-        group[i] = key;
-        local[i] = -1;
+        if (digit_of(key[g.cw[l]], g.cs[l], g.cd[l]) != g.cv[l]) return -1;
+    int a = 0, w = 1;
+    for (int l = 0; l < g.k; ++l) {
+        const uint32_t dg = digit_of(key[g.tw[l]], g.ts[l], g.td[l]);
+        a += (int)dg * w;
+        w *= (int)g.td[l];
+        key[g.tw[l]] -= (uint64_t)dg * g.ts[l];
     }
-    idx[i] = (uint32_t)i;
+    return a;
 }
 
-// Thread i owns output slots i * M .. i * M + M - 1.
-__global__ void sparse_classes(const uint64_t* __restrict__ sgroup, const uint32_t* __restrict__ sidx, uint64_t n,
-                               const int32_t* __restrict__ local, const double2* __restrict__ amps,
-                               const double2* __restrict__ U, const SparseGate g, uint64_t* __restrict__ okeys,
-                               double2* __restrict__ oamps, uint8_t* __restrict__ oflag) {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int M = g.M;
-    uint8_t* flag = oflag + i * M;
-    for (int r = 0; r < M; ++r) flag[r] = 0;
-    const uint64_t gk = sgroup[i];
-    if (i > 0 && sgroup[i - 1] == gk) return;  // not the group's first entry
-    const uint32_t e0 = sidx[i];
-    if (local[e0] < 0) {  // controls fail: unchanged
-        okeys[i * M] = gk;
-        oamps[i * M] = amps[e0];
-        flag[0] = 1;
+// Row r of U x over the present members of a class (bit a of `present`), in
+// ascending a, as textbook complex products with no FMA contraction: which
+// results are exactly zero (and dropped) then does not depend on how the
+// compiler would fuse them.
+__device__ __forceinline__ double2 class_row(const double2* U, const double2 (&x)[kSparseMaxM], uint32_t present,
+                                             int r, int M) {
+#pragma clang fp contract(off)
+    double yr = 0.0, yi = 0.0;
+    for (int a = 0; a < M; ++a) {
+        if (!((present >> a) & 1u)) continue;
+        const double2 u = U[r * M + a];
+        yr = yr + (u.x * x[a].x - u.y * x[a].y);
+        yi = yi + (u.x * x[a].y + u.y * x[a].x);
+    }
+    return double2{yr, yi};
+}
+
+// The whole gate in one workgroup. Input: n = nin[0] entries (key words
+// kin[w * cin + i], amplitudes ain[i]); output: the sorted kept results at kout /
+// aout (capacity cout) and their count at nout[0]. Entry i's results go to
+// output slots i * M .. i * M + M - 1 (only a group's first entry fills them).
+__global__ __launch_bounds__(kSmallThreads) void sparse_small(const uint64_t* __restrict__ kin,
+                                                              const double2* __restrict__ ain, uint64_t cin,
+                                                              uint64_t* __restrict__ counts, int src, int dst,
+                                                              uint64_t* __restrict__ kout, double2* __restrict__ aout,
+                                                              uint64_t cout, const SparseGate g) {
+    __shared__ uint64_t gk[kKeyWords][kSmallIn];
+    __shared__ int32_t la[kSmallIn];
+    __shared__ uint64_t ok[kKeyWords][kSparseSmallCap];
+    __shared__ double2 oa[kSparseSmallCap];
+    __shared__ uint8_t of[kSparseSmallCap];
+    __shared__ double2 su[kSparseMaxM * kSparseMaxM];
+    __shared__ uint32_t kept;
+    const uint32_t tid = threadIdx.x;
+    const int W = g.W, M = g.M;
+    const uint64_t n64 = counts[src];
+    if (n64 > kSmallIn || n64 * (uint64_t)M > kSparseSmallCap) {  // the host's bound was wrong: report, change nothing
+        if (tid == 0) counts[kErrWord] = 1;
         return;
     }
-    double2 x[kSparseMaxM];
-    for (int a = 0; a < M; ++a) x[a] = double2{0.0, 0.0};
-    for (uint64_t j = i; j < n && sgroup[j] == gk; ++j) {
-        const uint32_t e = sidx[j];
-        x[local[e]] = amps[e];
+    const uint32_t n = (uint32_t)n64, T = n * (uint32_t)M;
+    auto same = [&](uint32_t i, uint32_t j) {
+        for (int w = 0; w < W; ++w)
+            if (gk[w][i] != gk[w][j]) return false;
+        return true;
+    };
+    auto less = [&](uint32_t s, uint32_t t) {  // key of output s < key of output t
+        for (int w = W - 1; w >= 0; --w)
+            if (ok[w][s] != ok[w][t]) return ok[w][s] < ok[w][t];
+        return false;
+    };
+    for (uint32_t i = tid; i < (uint32_t)(M * M); i += kSmallThreads) su[i] = g.U[i];
+    for (uint32_t i = tid; i < n; i += kSmallThreads) {
+        uint64_t key[kKeyWords] = {0, 0, 0};
+        for (int w = 0; w < W; ++w) key[w] = kin[w * cin + i];
+        la[i] = classify(g, key);
+        for (int w = 0; w < kKeyWords; ++w) gk[w][i] = key[w];
     }
-    {
-        // Textbook complex products, no FMA contraction: which results are
-        // exactly zero (and dropped) then does not depend on how the compiler
-        // fuses them.
-#pragma clang fp contract(off)
-        for (int r = 0; r < M; ++r) {
-            double yr = 0.0, yi = 0.0;
-            for (int a = 0; a < M; ++a) {
-                const double2 u = U[r * M + a];
-                yr = yr + (u.x * x[a].x - u.y * x[a].y);
-                yi = yi + (u.x * x[a].y + u.y * x[a].x);
+    for (uint32_t s = tid; s < T; s += kSmallThreads) of[s] = 0;
+    if (tid == 0) kept = 0;
+    __syncthreads();
+    for (uint32_t i = tid; i < n; i += kSmallThreads) {
+        bool lead = true;
+        for (uint32_t j = 0; j < i; ++j)
+            if (same(i, j)) {
+                lead = false;
+                break;
             }
-            okeys[i * M + r] = gk + g.off[r];
-            oamps[i * M + r] = double2{yr, yi};
-            flag[r] = (yr != 0.0 || yi != 0.0) ? 1 : 0;
+        if (!lead) continue;
+        const uint32_t o = i * (uint32_t)M;
+        if (la[i] < 0) {  // controls fail: unchanged
+            for (int w = 0; w < kKeyWords; ++w) ok[w][o] = gk[w][i];
+            oa[o] = ain[i];
+            of[o] = 1;
+            continue;
+        }
+        double2 x[kSparseMaxM];
+        for (int a = 0; a < kSparseMaxM; ++a) x[a] = double2{0.0, 0.0};
+        uint32_t present = 0;
+        for (uint32_t j = i; j < n; ++j)
+            if (same(i, j)) {
+                x[la[j]] = ain[j];
+                present |= 1u << la[j];
+            }
+        for (int r = 0; r < M; ++r) {
+            const double2 y = class_row(su, x, present, r, M);
+            for (int w = 0; w < kKeyWords; ++w) ok[w][o + r] = gk[w][i] + g.off[r][w];
+            oa[o + r] = y;
+            of[o + r] = (y.x != 0.0 || y.y != 0.0) ? 1 : 0;
         }
     }
+    __syncthreads();
+    uint32_t mine = 0;
+    for (uint32_t s = tid; s < T; s += kSmallThreads) mine += of[s];
+    if (mine) atomicAdd(&kept, mine);
+    // Each kept result goes to its rank among the kept keys (keys are distinct:
+    // classes are disjoint and control-failing keys meet no class).
+    for (uint32_t s = tid; s < T; s += kSmallThreads) {
+        if (!of[s]) continue;
+        uint32_t rank = 0;
+        for (uint32_t t = 0; t < T; ++t) rank += (of[t] && less(t, s)) ? 1u : 0u;
+        for (int w = 0; w < W; ++w) kout[w * cout + rank] = ok[w][s];
+        aout[rank] = oa[s];
+    }
+    __syncthreads();
+    if (tid == 0) counts[dst] = kept;
 }
 
-__global__ void gather_amps(const uint32_t* __restrict__ perm, const double2* __restrict__ src, uint64_t n,
-                            double2* __restrict__ dst) {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// ---- the multi-kernel form ------------------------------------------------------
+
+__global__ void wide_classify(const uint64_t* __restrict__ kin, uint64_t cin, uint32_t n, const SparseGate g,
+                              uint64_t* __restrict__ gk, int32_t* __restrict__ la, uint32_t* __restrict__ idx) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint64_t key[kKeyWords] = {0, 0, 0};
+    for (int w = 0; w < g.W; ++w) key[w] = kin[w * cin + i];
+    la[i] = classify(g, key);
+    for (int w = 0; w < g.W; ++w) gk[(uint64_t)w * n + i] = key[w];
+    idx[i] = i;
+}
+
+__global__ void gather_u64(const uint32_t* __restrict__ perm, const uint64_t* __restrict__ src, uint32_t n,
+                           uint64_t* __restrict__ dst) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) dst[i] = src[perm[i]];
 }
 
-__global__ void iota_u32(uint32_t* p, uint64_t n) {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = (uint32_t)i;
+// Thread i (a position in group order) fills output slots i * M .. i * M + M - 1
+// when it is its group's first entry.
+__global__ void wide_classes(const uint64_t* __restrict__ sg, const uint32_t* __restrict__ sidx, uint32_t n,
+                             const int32_t* __restrict__ la, const double2* __restrict__ ain,
+                             const double2* __restrict__ U, const SparseGate g, uint64_t* __restrict__ okeys,
+                             double2* __restrict__ oamps, uint8_t* __restrict__ oflag) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int W = g.W, M = g.M;
+    const uint64_t T = (uint64_t)n * (uint64_t)M;
+    const uint64_t o = (uint64_t)i * (uint64_t)M;
+    for (int r = 0; r < M; ++r) oflag[o + r] = 0;
+    auto same = [&](uint32_t a, uint32_t b) {
+        for (int w = 0; w < W; ++w)
+            if (sg[(uint64_t)w * n + a] != sg[(uint64_t)w * n + b]) return false;
+        return true;
+    };
+    if (i > 0 && same(i - 1, i)) return;  // not the group's first entry
+    const uint32_t e0 = sidx[i];
+    if (la[e0] < 0) {  // controls fail: unchanged
+        for (int w = 0; w < W; ++w) okeys[(uint64_t)w * T + o] = sg[(uint64_t)w * n + i];
+        oamps[o] = ain[e0];
+        oflag[o] = 1;
+        return;
+    }
+    double2 x[kSparseMaxM];
+    for (int a = 0; a < kSparseMaxM; ++a) x[a] = double2{0.0, 0.0};
+    uint32_t present = 0;
+    for (uint32_t j = i; j < n && same(i, j); ++j) {
+        const uint32_t e = sidx[j];
+        x[la[e]] = ain[e];
+        present |= 1u << la[e];
+    }
+    for (int r = 0; r < M; ++r) {
+        const double2 y = class_row(U, x, present, r, M);
+        for (int w = 0; w < W; ++w) okeys[(uint64_t)w * T + o + r] = sg[(uint64_t)w * n + i] + g.off[r][w];
+        oamps[o + r] = y;
+        oflag[o + r] = (y.x != 0.0 || y.y != 0.0) ? 1 : 0;
+    }
+}
+
+__global__ void gather_entries(const uint32_t* __restrict__ perm, const uint64_t* __restrict__ okeys,
+                               const double2* __restrict__ oamps, uint32_t m, uint64_t T, int W,
+                               uint64_t* __restrict__ kout, uint64_t cout, double2* __restrict__ aout) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const uint32_t p = perm[i];
+    for (int w = 0; w < W; ++w) kout[(uint64_t)w * cout + i] = okeys[(uint64_t)w * T + p];
+    aout[i] = oamps[p];
+}
+
+__global__ void iota_u32(uint32_t* __restrict__ p, uint32_t n) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = i;
+}
+
+__global__ void set_count(uint64_t* __restrict__ counts, int dst, uint64_t v) {
+    if (threadIdx.x == 0) counts[dst] = v;
+}
+
+// |0...0>: every key word 0, amplitude 1; counts {1, 0, no error}.
+__global__ void sparse_basis(uint64_t* __restrict__ keys, double2* __restrict__ amps, int W, uint64_t cap,
+                             uint64_t* __restrict__ counts) {
+    if (threadIdx.x != 0) return;
+    for (int w = 0; w < W; ++w) keys[(uint64_t)w * cap] = 0;
+    amps[0] = double2{1.0, 0.0};
+    counts[0] = 1;
+    counts[1] = 0;
+    counts[kErrWord] = 0;
 }
 
 unsigned blocks(uint64_t n) { return (unsigned)((n + 255) / 256); }
@@ -120,133 +269,239 @@ struct Carver {
     }
 };
 
-hipError_t grow(void** buf, size_t* have, size_t need) {
+// Grow-only device buffer; the stream is drained before the old one is freed.
+hipError_t grow(void** buf, size_t* have, size_t need, hipStream_t st) {
     if (*have >= need) return hipSuccess;
+    hipError_t e;
+    if (*buf && (e = hipStreamSynchronize(st)) != hipSuccess) return e;
     void* p = nullptr;
     const size_t want = need + need / 2;
-    hipError_t e = hipMalloc(&p, want);
-    if (e != hipSuccess) return e;
+    if ((e = hipMalloc(&p, want)) != hipSuccess) return e;
     if (*buf) (void)hipFree(*buf);
     *buf = p;
     *have = want;
     return hipSuccess;
 }
 
+hipError_t grow_slot(SparseData& d, int i, uint64_t entries) {
+    if (d.slot_cap[i] >= entries) return hipSuccess;
+    size_t have = d.slot[i] ? slot_bytes(d.W, d.slot_cap[i]) : 0;
+    const uint64_t cap = std::max<uint64_t>(entries + entries / 2, kSparseSmallCap);
+    hipError_t e = grow(&d.slot[i], &have, slot_bytes(d.W, cap), d.stream);
+    if (e != hipSuccess) return e;
+    d.slot_cap[i] = cap;
+    return hipSuccess;
+}
+
+#define QD_TRY(x)                            \
+    do {                                     \
+        hipError_t e_ = (x);                 \
+        if (e_ != hipSuccess) return e_;     \
+    } while (0)
+
+hipError_t apply_small(SparseData& d, const SparseGate& g) {
+    const int nxt = d.cur ^ 1;
+    hipLaunchKernelGGL(sparse_small, dim3(1), dim3(kSmallThreads), 0, d.stream, slot_keys(d.slot[d.cur]),
+                       slot_amps(d.slot[d.cur], d.W, d.slot_cap[d.cur]), d.slot_cap[d.cur], d.nnz_dev, d.cur, nxt,
+                       slot_keys(d.slot[nxt]), slot_amps(d.slot[nxt], d.W, d.slot_cap[nxt]), d.slot_cap[nxt], g);
+    QD_TRY(hipGetLastError());
+    d.cur = nxt;
+    return hipSuccess;
+}
+
+// n = the exact entry count (> 0). Reads the kept count back once.
+hipError_t apply_wide(SparseData& d, SparseGate g, uint32_t n) {
+    const int W = d.W, M = g.M;
+    const uint64_t T = (uint64_t)n * (uint64_t)M;
+    hipStream_t st = d.stream;
+    size_t tb_n = 0, tb_sel = 0, tb_T = 0;
+    QD_TRY(hipcub::DeviceRadixSort::SortPairs(nullptr, tb_n, (uint64_t*)nullptr, (uint64_t*)nullptr,
+                                              (uint32_t*)nullptr, (uint32_t*)nullptr, (int)n));
+    QD_TRY(hipcub::DeviceSelect::Flagged(nullptr, tb_sel, (uint32_t*)nullptr, (uint8_t*)nullptr,
+                                         (uint32_t*)nullptr, (int*)nullptr, (int)T));
+    QD_TRY(hipcub::DeviceRadixSort::SortPairs(nullptr, tb_T, (uint64_t*)nullptr, (uint64_t*)nullptr,
+                                              (uint32_t*)nullptr, (uint32_t*)nullptr, (int)T));
+    const size_t tb = std::max(tb_n, std::max(tb_sel, tb_T));
+    struct Parts {
+        uint64_t *gk, *sg, *tk0, *tk1, *okeys;
+        int32_t* la;
+        uint32_t *pA, *pB, *pos;
+        double2 *dU, *oamps;
+        uint8_t* oflag;
+        int* nsel;
+        void* temp;
+    } p;
+    auto carve = [&](Carver& c) {
+        p.gk = c.take<uint64_t>((size_t)W * n * 8);
+        p.sg = c.take<uint64_t>((size_t)W * n * 8);
+        p.tk0 = c.take<uint64_t>(T * 8);
+        p.tk1 = c.take<uint64_t>(T * 8);
+        p.okeys = c.take<uint64_t>((size_t)W * T * 8);
+        p.la = c.take<int32_t>((size_t)n * 4);
+        p.pA = c.take<uint32_t>(T * 4);
+        p.pB = c.take<uint32_t>(T * 4);
+        p.pos = c.take<uint32_t>(T * 4);
+        p.dU = c.take<double2>((size_t)M * M * 16);
+        p.oamps = c.take<double2>(T * 16);
+        p.oflag = c.take<uint8_t>(T);
+        p.nsel = c.take<int>(sizeof(int));
+        p.temp = c.take<void>(tb);
+    };
+    Carver sizing{nullptr};
+    carve(sizing);
+    QD_TRY(grow(&d.work, &d.work_bytes, sizing.used, st));
+    Carver c{static_cast<unsigned char*>(d.work)};
+    carve(c);
+
+    const uint64_t* kin = slot_keys(d.slot[d.cur]);
+    const double2* ain = slot_amps(d.slot[d.cur], W, d.slot_cap[d.cur]);
+    QD_TRY(hipMemcpyAsync(p.dU, g.U, (size_t)M * M * 16, hipMemcpyHostToDevice, st));
+    g.U = p.dU;
+    hipLaunchKernelGGL(wide_classify, dim3(blocks(n)), dim3(256), 0, st, kin, d.slot_cap[d.cur], n, g, p.gk, p.la,
+                       p.pA);
+    QD_TRY(hipGetLastError());
+    // Group order: stable sorts by the group words, least significant word first.
+    for (int w = 0; w < W; ++w) {
+        const uint64_t* kw = p.gk + (size_t)w * n;
+        if (w > 0) {
+            hipLaunchKernelGGL(gather_u64, dim3(blocks(n)), dim3(256), 0, st, p.pA, kw, n, p.tk0);
+            QD_TRY(hipGetLastError());
+            kw = p.tk0;
+        }
+        size_t t = tb;
+        QD_TRY(hipcub::DeviceRadixSort::SortPairs(p.temp, t, kw, p.tk1, p.pA, p.pB, (int)n, 0, 64, st));
+        std::swap(p.pA, p.pB);
+    }
+    for (int w = 0; w < W; ++w) {
+        hipLaunchKernelGGL(gather_u64, dim3(blocks(n)), dim3(256), 0, st, p.pA, p.gk + (size_t)w * n, n,
+                           p.sg + (size_t)w * n);
+        QD_TRY(hipGetLastError());
+    }
+    hipLaunchKernelGGL(wide_classes, dim3(blocks(n)), dim3(256), 0, st, p.sg, p.pA, n, p.la, ain, p.dU, g, p.okeys,
+                       p.oamps, p.oflag);
+    QD_TRY(hipGetLastError());
+    hipLaunchKernelGGL(iota_u32, dim3(blocks(T)), dim3(256), 0, st, p.pos, (uint32_t)T);
+    QD_TRY(hipGetLastError());
+    size_t t = tb;
+    QD_TRY(hipcub::DeviceSelect::Flagged(p.temp, t, p.pos, p.oflag, p.pB, p.nsel, (int)T, st));
+    int h_sel = 0;
+    QD_TRY(hipMemcpyAsync(&h_sel, p.nsel, sizeof(int), hipMemcpyDeviceToHost, st));
+    QD_TRY(hipStreamSynchronize(st));  // the one read-back of the multi-kernel form
+    const uint32_t m = (uint32_t)h_sel;
+
+    const int nxt = d.cur ^ 1;
+    QD_TRY(grow_slot(d, nxt, m));
+    if (m > 0) {
+        uint32_t* perm = p.pB;
+        uint32_t* spare = p.pA;
+        for (int w = 0; w < W; ++w) {
+            hipLaunchKernelGGL(gather_u64, dim3(blocks(m)), dim3(256), 0, st, perm, p.okeys + (size_t)w * T, m,
+                               p.tk0);
+            QD_TRY(hipGetLastError());
+            size_t t3 = tb;
+            QD_TRY(hipcub::DeviceRadixSort::SortPairs(p.temp, t3, p.tk0, p.tk1, perm, spare, (int)m, 0, 64, st));
+            std::swap(perm, spare);
+        }
+        hipLaunchKernelGGL(gather_entries, dim3(blocks(m)), dim3(256), 0, st, perm, p.okeys, p.oamps, m, T, W,
+                           slot_keys(d.slot[nxt]), d.slot_cap[nxt], slot_amps(d.slot[nxt], W, d.slot_cap[nxt]));
+        QD_TRY(hipGetLastError());
+    }
+    hipLaunchKernelGGL(set_count, dim3(1), dim3(64), 0, st, d.nnz_dev, nxt, (uint64_t)m);
+    QD_TRY(hipGetLastError());
+    d.cur = nxt;
+    d.bound = m;
+    d.exact = true;
+    return hipSuccess;
+}
+
 }  // namespace
 
-hipError_t sparse_init(SparseData& d) {
-    size_t have = d.slot_bytes[0];
-    hipError_t e = grow(&d.slot[0], &have, 256 + 16);
-    if (e != hipSuccess) return e;
-    d.slot_bytes[0] = have;
+hipError_t sparse_init(SparseData& d, int W) {
+    d.W = W;
+    hipError_t e;
+    for (int i = 0; i < 2; ++i)
+        if ((e = grow_slot(d, i, kSparseSmallCap)) != hipSuccess) return e;
+    size_t have = 0;
+    void* counts = nullptr;
+    if ((e = grow(&counts, &have, 3 * sizeof(uint64_t), d.stream)) != hipSuccess) return e;
+    d.nnz_dev = static_cast<uint64_t*>(counts);
+    if ((e = hipHostMalloc(reinterpret_cast<void**>(&d.uhost),
+                           sizeof(double2) * kSparseMaxM * kSparseMaxM * SparseData::kURing, hipHostMallocDefault)) !=
+        hipSuccess) {
+        d.uhost = nullptr;
+        return e;
+    }
+    void* udev = nullptr;
+    if ((e = hipHostGetDevicePointer(&udev, d.uhost, 0)) != hipSuccess) return e;
+    d.udev = static_cast<double2*>(udev);
+    for (int i = 0; i < SparseData::kURing; ++i)
+        if ((e = hipEventCreateWithFlags(&d.uev[i], hipEventDisableTiming)) != hipSuccess) return e;
+    hipLaunchKernelGGL(sparse_basis, dim3(1), dim3(64), 0, d.stream, slot_keys(d.slot[0]),
+                       slot_amps(d.slot[0], W, d.slot_cap[0]), W, d.slot_cap[0], d.nnz_dev);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     d.cur = 0;
-    d.keys = static_cast<uint64_t*>(d.slot[0]);
-    d.amps = reinterpret_cast<double2*>(static_cast<unsigned char*>(d.slot[0]) + 256);
-    const uint64_t key0 = 0;
-    const double2 amp0{1.0, 0.0};
-    if ((e = hipMemcpy(d.keys, &key0, 8, hipMemcpyHostToDevice)) != hipSuccess) return e;
-    if ((e = hipMemcpy(d.amps, &amp0, 16, hipMemcpyHostToDevice)) != hipSuccess) return e;
-    d.nnz = 1;
-    return hipSuccess;
+    d.bound = 1;
+    d.exact = true;
+    return hipStreamSynchronize(d.stream);
 }
 
 void sparse_release(SparseData& d) {
+    (void)hipStreamSynchronize(d.stream);
     for (int i = 0; i < 2; ++i)
         if (d.slot[i]) (void)hipFree(d.slot[i]);
     if (d.work) (void)hipFree(d.work);
+    if (d.nnz_dev) (void)hipFree(d.nnz_dev);
+    for (int i = 0; i < SparseData::kURing; ++i)
+        if (d.uev[i]) (void)hipEventDestroy(d.uev[i]);
+    if (d.uhost) (void)hipHostFree(d.uhost);
     d = SparseData{};
 }
 
-hipError_t sparse_apply(SparseData& d, const SparseGate& g, const double* U) {
-    const uint64_t n = d.nnz;
-    if (n == 0) return hipSuccess;
-    // hipCUB counts items in int: the M results per entry must stay below 2^31
-    if (n > (uint64_t)INT32_MAX / (uint64_t)g.M) return hipErrorInvalidValue;
-    const uint64_t cap = n * (uint64_t)g.M;
-    hipError_t e;
-#define QD_TRY(x) \
-    if ((e = (x)) != hipSuccess) return e
-    // Temporary storage of the three library calls, at their largest sizes.
-    size_t tb_sort1 = 0, tb_sel = 0, tb_sort2 = 0;
-    QD_TRY(hipcub::DeviceRadixSort::SortPairs(nullptr, tb_sort1, (uint64_t*)nullptr, (uint64_t*)nullptr,
-                                              (uint32_t*)nullptr, (uint32_t*)nullptr, (int)n));
-    QD_TRY(hipcub::DeviceSelect::Flagged(nullptr, tb_sel, (uint64_t*)nullptr, (uint8_t*)nullptr,
-                                         (uint64_t*)nullptr, (int*)nullptr, (int)cap));
-    QD_TRY(hipcub::DeviceRadixSort::SortPairs(nullptr, tb_sort2, (uint64_t*)nullptr, (uint64_t*)nullptr,
-                                              (uint32_t*)nullptr, (uint32_t*)nullptr, (int)cap));
-    const size_t tb = std::max(tb_sort1, std::max(tb_sel, tb_sort2));
-    auto carve = [&](Carver& c, uint64_t** group, uint64_t** sgroup, int32_t** local, uint32_t** idx,
-                     uint32_t** sidx, double2** dU, void** temp, uint64_t** okeys, double2** oamps, uint8_t** oflag,
-                     uint32_t** pos, uint32_t** kpos, uint32_t** spos, uint64_t** kkeys, int** nsel) {
-        *group = c.take<uint64_t>(n * 8);
-        *sgroup = c.take<uint64_t>(n * 8);
-        *local = c.take<int32_t>(n * 4);
-        *idx = c.take<uint32_t>(n * 4);
-        *sidx = c.take<uint32_t>(n * 4);
-        *dU = c.take<double2>((size_t)g.M * g.M * 16);
-        *temp = c.take<void>(tb);
-        *okeys = c.take<uint64_t>(cap * 8);
-        *oamps = c.take<double2>(cap * 16);
-        *oflag = c.take<uint8_t>(cap);
-        *pos = c.take<uint32_t>(cap * 4);
-        *kpos = c.take<uint32_t>(cap * 4);
-        *spos = c.take<uint32_t>(cap * 4);
-        *kkeys = c.take<uint64_t>(cap * 8);
-        *nsel = c.take<int>(sizeof(int));
-    };
-    uint64_t *group, *sgroup, *okeys, *kkeys;
-    int32_t* local;
-    uint32_t *idx, *sidx, *pos, *kpos, *spos;
-    double2 *dU, *oamps;
-    uint8_t* oflag;
-    void* temp;
-    int* nsel;
-    Carver sizing{nullptr};
-    carve(sizing, &group, &sgroup, &local, &idx, &sidx, &dU, &temp, &okeys, &oamps, &oflag, &pos, &kpos, &spos,
-          &kkeys, &nsel);
-    QD_TRY(grow(&d.work, &d.work_bytes, sizing.used));
-    Carver c{static_cast<unsigned char*>(d.work)};
-    carve(c, &group, &sgroup, &local, &idx, &sidx, &dU, &temp, &okeys, &oamps, &oflag, &pos, &kpos, &spos, &kkeys,
-          &nsel);
-
-    QD_TRY(hipMemcpy(dU, U, (size_t)g.M * g.M * 16, hipMemcpyHostToDevice));
-    hipLaunchKernelGGL(sparse_classify, dim3(blocks(n)), dim3(256), 0, 0, d.keys, n, g, group, local, idx);
-    QD_TRY(hipGetLastError());
-    size_t t1 = tb;
-    QD_TRY(hipcub::DeviceRadixSort::SortPairs(temp, t1, group, sgroup, idx, sidx, (int)n));
-    hipLaunchKernelGGL(sparse_classes, dim3(blocks(n)), dim3(256), 0, 0, sgroup, sidx, n, local, d.amps, dU, g,
-                       okeys, oamps, oflag);
-    QD_TRY(hipGetLastError());
-    // Keep the flagged results (keys, and their positions), then sort them by key.
-    hipLaunchKernelGGL(iota_u32, dim3(blocks(cap)), dim3(256), 0, 0, pos, cap);
-    QD_TRY(hipGetLastError());
-    size_t t2 = tb;
-    QD_TRY(hipcub::DeviceSelect::Flagged(temp, t2, okeys, oflag, kkeys, nsel, (int)cap));
-    t2 = tb;
-    QD_TRY(hipcub::DeviceSelect::Flagged(temp, t2, pos, oflag, kpos, nsel, (int)cap));
-    int h_sel = 0;
-    QD_TRY(hipMemcpy(&h_sel, nsel, sizeof(int), hipMemcpyDeviceToHost));
-    const uint64_t m = (uint64_t)h_sel;
-
-    // The result goes to the other slot.
-    const int nxt = d.cur ^ 1;
-    const size_t kbytes = up256(m * 8 + 1);
-    QD_TRY(grow(&d.slot[nxt], &d.slot_bytes[nxt], kbytes + m * 16 + 16));
-    uint64_t* nkeys = static_cast<uint64_t*>(d.slot[nxt]);
-    double2* namps = reinterpret_cast<double2*>(static_cast<unsigned char*>(d.slot[nxt]) + kbytes);
-    if (m > 0) {
-        size_t t3 = tb;
-        QD_TRY(hipcub::DeviceRadixSort::SortPairs(temp, t3, kkeys, nkeys, kpos, spos, (int)m));
-        hipLaunchKernelGGL(gather_amps, dim3(blocks(m)), dim3(256), 0, 0, spos, oamps, m, namps);
-        QD_TRY(hipGetLastError());
-    }
-    QD_TRY(hipDeviceSynchronize());
-#undef QD_TRY
-    d.cur = nxt;
-    d.keys = nkeys;
-    d.amps = namps;
-    d.nnz = m;
+hipError_t sparse_count(SparseData& d, uint64_t* nnz) {
+    QD_TRY(hipStreamSynchronize(d.stream));
+    uint64_t h[3] = {0, 0, 0};
+    QD_TRY(hipMemcpy(h, d.nnz_dev, sizeof h, hipMemcpyDeviceToHost));
+    if (h[kErrWord]) return hipErrorIllegalState;  // a small gate found more entries than the host planned for
+    *nnz = h[d.cur];
+    d.bound = *nnz;
+    d.exact = true;
     return hipSuccess;
 }
+
+hipError_t sparse_apply(SparseData& d, const SparseGate& g0, const double* U, bool cols_single) {
+    const uint64_t M = (uint64_t)g0.M;
+    if (d.bound > kSparseSmallCap / M && !d.exact) {
+        uint64_t n = 0;
+        QD_TRY(sparse_count(d, &n));
+    }
+    if (d.bound == 0) return hipSuccess;  // no entries: nothing to do
+    const bool small = d.bound <= kSparseSmallCap / M;
+    if (!small && d.bound * M > (uint64_t)INT32_MAX) return hipErrorNotSupported;  // hipCUB counts items in int
+    // Stage U in the pinned ring (the slot's previous gate has finished once its event has).
+    const int slot = (int)(d.uses % SparseData::kURing);
+    if (d.uses >= (uint64_t)SparseData::kURing) QD_TRY(hipEventSynchronize(d.uev[slot]));
+    double2* uh = d.uhost + (size_t)slot * kSparseMaxM * kSparseMaxM;
+    std::memcpy(uh, U, M * M * sizeof(double2));
+    SparseGate g = g0;
+    g.U = d.udev + (uh - d.uhost);
+    hipError_t e;
+    if (small) {
+        e = apply_small(d, g);
+        if (e == hipSuccess) {
+            d.bound = cols_single ? d.bound : d.bound * M;
+            d.exact = false;
+        }
+    } else {
+        g.U = uh;  // copied to device memory by the multi-kernel form
+        e = apply_wide(d, g, (uint32_t)d.bound);
+    }
+    // Whatever was enqueued may still read the staged matrix: the slot is
+    // reused only after this event.
+    const hipError_t er = hipEventRecord(d.uev[slot], d.stream);
+    ++d.uses;
+    return e != hipSuccess ? e : er;
+}
+
+#undef QD_TRY
 
 }  // namespace qd

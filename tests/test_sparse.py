@@ -68,6 +68,34 @@ def test_sparse_oracle_ghz_closed_form(d, n):
     assert st == ghz_closed_form(d, n)
 
 
+# Registers past the signed 64-bit index of the paper's sparse runs (Sec. 3),
+# reached with wider keys (Sec. 4): two key words, and three for 7^45.
+WIDE_GHZ = [(2, 100), (3, 63), (4, 50), (5, 43), (7, 45), (2, 126)]
+
+
+@pytest.mark.parametrize("d,n", WIDE_GHZ)
+def test_sparse_oracle_ghz_closed_form_wide(d, n):
+    assert d ** n < 2**127
+    st = soracle.run([d] * n, ghz_gates(d, n))
+    assert st == ghz_closed_form(d, n)
+
+
+def test_sparse_register_limits_host():
+    # D = prod dims as a 128-bit value, and the key words (qudits packed from q0
+    # while the product of a word's dims stays below 2^64).
+    for dims, words in (([2] * 63, 1), ([2] * 64, 2), ([2] * 126, 2), ([3] * 80, 2), ([4] * 63, 3), ([5] * 54, 2),
+                        ([7] * 45, 3), ([7] * 22 + [2] * 3, 2), ([2] * 62, 1)):
+        D, w = qd().sparse_dim(dims)
+        assert D == math.prod(dims) and w == words, (dims, D, w)
+    for dims in ([2] * 125 + [5], [3] * 81, [5] * 55, [7] * 46, [4] * 64):
+        with pytest.raises(qd().QDError) as e:
+            qd().sparse_dim(dims)
+        assert e.value.code == -2  # QD_ERR_DIM_OVERFLOW: D >= 2^127
+    for dims in ([], [2] * 127 + [1], [2, 8], [1, 2]):
+        with pytest.raises(qd().QDError):
+            qd().sparse_dim(dims)
+
+
 def test_sparse_oracle_drops_exact_zeros():
     h = np.array([[1.0, 1.0], [1.0, -1.0]]) / math.sqrt(2.0)  # real entries: h*h - h*h is exactly 0
     st = soracle.apply([2, 2], soracle.zero_state([2, 2]), (0,), h)
@@ -87,6 +115,7 @@ def qd():
 def gpu_dict(st):
     keys, amps = st.entries()
     return {int(k): complex(a) for k, a in zip(keys, amps)}
+
 
 
 @pytest.mark.gpu
@@ -122,6 +151,93 @@ def test_sparse_gpu_ghz_at_the_largest_registers(d, n):
     ref = soracle.run([d] * n, back, ghz_closed_form(d, n))
     assert gpu_dict(st) == ref
     assert abs(ref[0] - 1.0) < 1e-15 and all(abs(a) < 1e-15 for j, a in ref.items() if j)
+    st.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("d,n", WIDE_GHZ)
+def test_sparse_gpu_ghz_wide_keys(d, n):
+    # GHZ_d beyond 2^64 basis states: multi-word keys, entry for entry against
+    # the sparse oracle (Python integers) and the closed form, then back.
+    st = qd().SparseState([d] * n)
+    assert st.words == (3 if d == 7 else 2)
+    gates = ghz_gates(d, n)
+    for g in gates:
+        st.apply_gate(g)
+    assert st.nnz() == d
+    assert gpu_dict(st) == ghz_closed_form(d, n) == soracle.run([d] * n, gates)
+    back = list(reversed([g.inverse() for g in gates]))
+    for g in back:
+        st.apply_gate(g)
+    assert gpu_dict(st) == soracle.run([d] * n, back, ghz_closed_form(d, n))
+    st.close()
+
+
+WIDE_REGISTERS = [
+    [7] * 20 + [2, 3, 5, 7] * 3 + [3] * 10,   # D ~ 2^95: two key words, the first ends inside the 2,3,5,7 run
+    [7] * 45,                                 # D ~ 2^126: three key words
+    [2, 3] * 30 + [5] * 8,                    # D ~ 2^96: two key words
+]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("case", range(len(WIDE_REGISTERS)))
+def test_sparse_gpu_wide_random_circuits(case):
+    # Random gates with targets and controls in every key word, gate by gate
+    # against the sparse oracle. Superpositions act on five qudits spread over
+    # the words (so the state stays within tens of thousands of entries and the
+    # oracle stays quick), permutations and controlled shifts anywhere: the state
+    # goes from a few entries (one-workgroup form) to thousands (multi-kernel form).
+    dims = WIDE_REGISTERS[case]
+    n = len(dims)
+    S = [0, n // 3, n // 2, 2 * n // 3, n - 1]
+    rng = np.random.default_rng(40 + case)
+    st = qd().SparseState(dims)
+    ref = soracle.zero_state(dims)
+    biggest = 1
+    for i in range(70):
+        r = rng.random()
+        if r < 0.35:
+            t = int(rng.choice(S))
+            g = Gate((t,), haar(dims[t], rng) if rng.random() < 0.7 else dft(dims[t]))
+        elif r < 0.85:
+            c, t = (int(x) for x in rng.choice(n, 2, replace=False))
+            g = Gate((t,), shift(dims[t], int(rng.integers(1, dims[t]))), (c,), (int(rng.integers(dims[c])),))
+        else:
+            a, b = (int(x) for x in rng.choice(S, 2, replace=False))
+            if dims[a] * dims[b] > 16:
+                continue
+            g = Gate((a, b), haar(dims[a] * dims[b], rng))
+        st.apply_gate(g)
+        ref = soracle.apply(dims, ref, g.targets, g.U, g.controls, g.values)
+        biggest = max(biggest, len(ref) * g.M)
+        if i % 10 == 9 or i == 69:
+            got = gpu_dict(st)
+            print(f"[sparse wide {case}] gate {i}: {len(got)} entries", flush=True)
+            assert got == ref, f"gate {i}: {len(got)} vs {len(ref)} entries"
+            keys, _ = st.entries()
+            assert all(a < b for a, b in zip(keys, keys[1:]))
+    if case < 2:
+        assert biggest > 1024  # the multi-kernel form ran
+    st.close()
+
+
+@pytest.mark.gpu
+def test_sparse_gpu_switches_forms_on_the_true_count():
+    # Permutations keep the count, so the host's bound stays tight; dense gates
+    # raise the bound past the one-workgroup limit while the true count may
+    # stay low (here each DFT is undone), which makes the host read the count
+    # back and go on in the one-workgroup form.
+    dims = [3] * 70
+    st = qd().SparseState(dims)
+    ref = soracle.zero_state(dims)
+    gates = []
+    for q in range(8):
+        gates += [Gate((q,), dft(3)), Gate((q,), dft(3).conj().T), Gate((q + 10,), shift(3), (q,), (0,))]
+    for g in gates:
+        st.apply_gate(g)
+        ref = soracle.apply(dims, ref, g.targets, g.U, g.controls, g.values)
+    assert gpu_dict(st) == ref
     st.close()
 
 
