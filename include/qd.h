@@ -333,6 +333,27 @@ int qd_batch_plan_destroy(qd_batch_plan* plan);
  * states and serialised by a lock. */
 int qd_norm(const qd_state* s, double* out);
 
+/* ---- the norm without allocation --------------------------------------------------- */
+
+/* For callers that cannot allocate device memory or wait on a stream: code under
+ * HIP graph capture, serving loops that retire requests while others run, and
+ * harnesses that forbid hipMalloc. out[i] = ||states[i]||_2, the same value, bit
+ * for bit, as qd_norm (the same reduction in the same fixed order), written by
+ * the device on states[i]'s stream; out must be device-accessible (device memory,
+ * or pinned host memory from hipHostMalloc) with room for `count` doubles, and is
+ * valid once that stream has reached this point (synchronize it, or record and
+ * wait for an event after the call). The call allocates nothing and does not wait:
+ * the partial sums go to a fixed array of the library on each GPU
+ * (QD_NOALLOC_MAX_STATES x 1025 doubles, about 513 KB, held until the process
+ * ends), so count is 1..QD_NOALLOC_MAX_STATES (more give QD_ERR_NOT_SUPPORTED);
+ * every state must be on the current device and listed once. All calls on one
+ * GPU share that array and each call rewrites every partial it reads (nothing
+ * in it has to start at zero), so calls on one stream are ordered, but calls
+ * whose work can overlap in time (on different streams, or states of one call
+ * on different streams) race and give wrong norms. */
+#define QD_NOALLOC_MAX_STATES 64
+int qd_norm_noalloc(const qd_state* const* states, int32_t count, double* out);
+
 /* p_j = |a_j|^2 in FP64 for all j (Sec. 2: the squared amplitude of |j>).
  * out has len >= D doubles, on the device (location QD_DEVICE, written
  * asynchronously on the state's stream) or on the host (QD_HOST, synchronous).

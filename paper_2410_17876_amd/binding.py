@@ -83,6 +83,7 @@ def _load() -> C.CDLL:
         "qd_sparse_get": [vp, u64p, f64p, C.c_uint64],
         "qd_sparse_get_wide": [vp, u64p, f64p, C.c_uint64],
         "qd_norm": [vp, f64p],
+        "qd_norm_noalloc": [C.POINTER(vp), C.c_int32, vp],
         "qd_probabilities": [vp, f64p, C.c_uint64, C.c_int32],
         "qd_synchronize": [vp],
         "qd_copy_ceiling": [vp, C.c_int32, f64p],
@@ -360,6 +361,15 @@ class State:
             self.close()
         except Exception:
             pass
+
+
+def norm_noalloc(states, out) -> None:
+    """qd_norm_noalloc: enqueue the FP64 norms of `states` into `out`, a float64
+    torch tensor on their device (or a pinned host tensor) with room for one
+    value per state; allocates nothing and does not wait (read `out` after the
+    states' streams have reached this call)."""
+    hs = (C.c_void_p * max(1, len(states)))(*[st.handle for st in states])
+    check(lib.qd_norm_noalloc(hs, len(states), C.c_void_p(out.data_ptr())))
 
 
 def _batch_args(states, gate_lists):

@@ -1147,16 +1147,72 @@ int qd_norm(const qd_state* s, double* out) {
     std::lock_guard<std::mutex> lock(g_red_mu);
     double*& red = g_red[s->device];
     if (!red) {
-        if (hipMalloc(reinterpret_cast<void**>(&red), (kRedBlocks + 1) * sizeof(double)) != hipSuccess) {
+        if (hipMalloc(reinterpret_cast<void**>(&red), (kRedScratch + 1) * sizeof(double)) != hipSuccess) {
             red = nullptr;
             return set_err(QD_ERR_OUT_OF_MEMORY, "reduction scratch allocation failed");
         }
     }
-    QD_HIP(launch_sumsq(s->psi, s->precision, s->D, red, s->stream), "norm");
-    double sum = 0.0;
-    QD_HIP(hipMemcpyAsync(&sum, red + kRedBlocks, sizeof(double), hipMemcpyDeviceToHost, s->stream), "norm");
+    QD_HIP(launch_sumsq(s->psi, s->precision, s->D, red, red + kRedScratch, s->stream), "norm");
+    double nrm = 0.0;
+    QD_HIP(hipMemcpyAsync(&nrm, red + kRedScratch, sizeof(double), hipMemcpyDeviceToHost, s->stream), "norm");
     QD_HIP(hipStreamSynchronize(s->stream), "norm");
-    *out = std::sqrt(sum);
+    *out = nrm;
+    return QD_OK;
+}
+
+// ---- the norm without allocation --------------------------------------------------
+
+namespace {
+
+// Partial sums of qd_norm_noalloc: one region of kRedScratch doubles per state of
+// a call, in a fixed array of every GPU the library runs on (held until the
+// process ends). Host code never passes the array's name to a kernel: it uses
+// the device address hipGetSymbolAddress returns, one per device.
+static __device__ __align__(256) double scratch[QD_NOALLOC_MAX_STATES * kRedScratch];
+
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device (looked up once per device).
+int noalloc_scratch(int device, double** out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    double*& p = g_scratch_ptr[device];
+    if (!p) {
+        void* addr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_err(e, "looking up the no-allocation scratch");
+        p = static_cast<double*>(addr);
+    }
+    *out = p;
+    return QD_OK;
+}
+
+}  // namespace
+
+int qd_norm_noalloc(const qd_state* const* states, int32_t count, double* out) {
+    if (!states || !out) return set_err(QD_ERR_INVALID_ARGUMENT, "states or out is null");
+    if (count < 1) return set_err(QD_ERR_INVALID_ARGUMENT, "count must be at least 1");
+    if (count > QD_NOALLOC_MAX_STATES)
+        return set_err(QD_ERR_NOT_SUPPORTED, "qd_norm_noalloc takes at most QD_NOALLOC_MAX_STATES (64) states per "
+                                             "call; its fixed scratch holds the partial sums of 64 states");
+    int device = -1;
+    QD_HIP(hipGetDevice(&device), "hipGetDevice");
+    if (device < 0 || device >= kMaxDevices) return set_err(QD_ERR_NOT_SUPPORTED, "device index too large");
+    for (int32_t i = 0; i < count; ++i) {
+        if (!states[i]) return set_err(QD_ERR_INVALID_ARGUMENT, "a state is null");
+        if (states[i]->device != device)
+            return set_err(QD_ERR_INVALID_ARGUMENT, "every state must be on the current device");
+        for (int32_t j = 0; j < i; ++j)
+            if (states[j] == states[i]) return set_err(QD_ERR_INVALID_ARGUMENT, "a state is listed twice");
+    }
+    double* part = nullptr;
+    int rc = noalloc_scratch(device, &part);
+    if (rc) return rc;
+    for (int32_t i = 0; i < count; ++i) {
+        const qd_state* s = states[i];
+        QD_HIP(launch_sumsq(s->psi, s->precision, s->D, part + (size_t)i * kRedScratch, out + i, s->stream),
+               "norm without allocation");
+    }
     return QD_OK;
 }
 

@@ -61,8 +61,11 @@ hipError_t launch_batch(int precision, const void* ditems, int nitems, uint32_t 
 
 // Reductions and fills (reduce.hip).
 constexpr int kRedBlocks = 1024;
-hipError_t launch_sumsq(const void* psi, int precision, uint64_t D, double* scratch /* kRedBlocks+1 */,
-                        hipStream_t stream);  // result in scratch[kRedBlocks]
+constexpr int kRedScratch = kRedBlocks + 1;  // doubles of partial sums one reduction uses
+// Sum of squares into scratch[kRedBlocks] (scratch: kRedScratch doubles) and its
+// square root into *norm (device-accessible).
+hipError_t launch_sumsq(const void* psi, int precision, uint64_t D, double* scratch, double* norm,
+                        hipStream_t stream);
 hipError_t launch_probabilities(const void* psi, int precision, uint64_t offset, uint64_t count,
                                 double* out, hipStream_t stream);
 hipError_t launch_basis(void* psi, int precision, uint64_t D, uint64_t j, hipStream_t stream);

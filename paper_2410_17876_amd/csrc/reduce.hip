@@ -44,12 +44,16 @@ __global__ __launch_bounds__(256) void sumsq_partial(const T* __restrict__ psi, 
     if (threadIdx.x == 0) partial[blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(256) void sumsq_final(double* __restrict__ partial, int nb) {
+// partial[nb] = the sum of the nb partials (fixed tree); *norm = its square root.
+__global__ __launch_bounds__(256) void sumsq_final(double* __restrict__ partial, int nb, double* __restrict__ norm) {
     __shared__ double sh[256];
     double s = 0.0;
     for (int i = threadIdx.x; i < nb; i += 256) s += partial[i];
     const double tot = block_sum(s, sh);
-    if (threadIdx.x == 0) partial[nb] = tot;
+    if (threadIdx.x == 0) {
+        partial[nb] = tot;
+        *norm = sqrt(tot);
+    }
 }
 
 template <typename T>
@@ -105,14 +109,14 @@ static unsigned grid_for(uint64_t n) {
     return (unsigned)(b < 8192 ? (b ? b : 1) : 8192);
 }
 
-hipError_t launch_sumsq(const void* psi, int precision, uint64_t D, double* scratch, hipStream_t st) {
+hipError_t launch_sumsq(const void* psi, int precision, uint64_t D, double* scratch, double* norm, hipStream_t st) {
     if (precision == kC128)
         hipLaunchKernelGGL(sumsq_partial<double2>, dim3(kRedBlocks), dim3(256), 0, st,
                            static_cast<const double2*>(psi), D, scratch);
     else
         hipLaunchKernelGGL(sumsq_partial<float2>, dim3(kRedBlocks), dim3(256), 0, st,
                            static_cast<const float2*>(psi), D, scratch);
-    hipLaunchKernelGGL(sumsq_final, dim3(1), dim3(256), 0, st, scratch, kRedBlocks);
+    hipLaunchKernelGGL(sumsq_final, dim3(1), dim3(256), 0, st, scratch, kRedBlocks, norm);
     return hipGetLastError();
 }
 
