@@ -9,7 +9,10 @@ call (qd_batch_apply: one launch per round across all requests). A request that 
 are running is admitted at the next tick as soon as a slot and enough of the
 HBM budget are free; a finished request's memory is released at once. The host
 prepares tick k+1 while the device runs tick k; completion is observed through
-one HIP event per tick.
+one HIP event per tick. A request's FP64 norm is enqueued right after its last
+gates (qd_norm_noalloc, written by the device into pinned host memory), so
+retiring it reads a finished value and never waits on the stream the other
+requests share.
 
 Per-request arithmetic does not depend on the mix: a fused pass applies each of
 its gates with the same per-class arithmetic as a lone gate, so a request's
@@ -30,7 +33,7 @@ from typing import Deque, Dict, List, Optional, Sequence
 
 import numpy as np
 
-from .binding import Batch, GateList, State
+from .binding import Batch, GateList, State, norm_noalloc
 
 
 @dataclass
@@ -46,6 +49,7 @@ class ServeRequest:
     pos: int = 0                   # gates already enqueued
     done_tick: Optional[int] = None
     rejected: bool = False
+    slot: int = -1                 # entry of the server's pinned norm buffer
 
     @property
     def D(self) -> int:
@@ -86,6 +90,10 @@ class Server:
         self.events: Dict[int, object] = {}
         self.t0 = time.perf_counter()
         self.max_resident = 0
+        # one pinned FP64 entry per slot: the device writes a finished request's
+        # norm there, and the host reads it once the tick's event has completed
+        self.norms = torch.zeros(max_slots, dtype=torch.float64, pin_memory=True)
+        self.free_slots = list(range(max_slots - 1, -1, -1))
 
     def state_bytes(self, r: ServeRequest) -> int:
         return r.D * self.amp_bytes
@@ -104,6 +112,7 @@ class Server:
                 break  # FIFO: wait for memory to free up
             self.queue.popleft()
             r.state = State(r.dims, self.precision, init=0, stream=self.stream)
+            r.slot = self.free_slots.pop()
             r.admitted = now
             self.resident.append(r)
             self.resident_bytes += self.state_bytes(r)
@@ -114,8 +123,10 @@ class Server:
         keep = []
         for r in self.resident:
             if r.done_tick is not None and self.events[r.done_tick].query():
-                r.norm = r.state.norm()  # FP64 norm returned to the host: the request is complete
+                r.norm = float(self.norms[r.slot])  # FP64 norm on the host: the request is complete
                 r.finished = time.perf_counter() - self.t0
+                self.free_slots.append(r.slot)
+                r.slot = -1
                 if not self.keep_states:
                     r.state.close()
                     r.state = None
@@ -129,23 +140,28 @@ class Server:
             del self.events[t]
 
     def _tick(self) -> bool:
-        """Enqueue the next quantum of every resident request; False if none had work."""
+        """Enqueue the next quantum of every resident request, and the norm of every
+        request whose gates are now all enqueued (an empty circuit included);
+        False if there was nothing to enqueue."""
         work = [r for r in self.resident if r.pos < len(r.gates)]
-        if not work:
+        if work:
+            lists = []
+            for r in work:
+                q = max(self.quantum, int(self.tick_updates // r.D))
+                lists.append(r.gates.view(r.pos, q))  # no re-marshalling per tick
+                r.pos += len(lists[-1])
+            self.batch.apply([r.state for r in work], lists, tile_amps=self.tile_amps, min_run=self.min_run,
+                             reorder=self.reorder)
+        finishing = [r for r in self.resident if r.done_tick is None and r.pos >= len(r.gates)]
+        if not work and not finishing:
             return False
-        lists = []
-        for r in work:
-            q = max(self.quantum, int(self.tick_updates // r.D))
-            lists.append(r.gates.view(r.pos, q))  # no re-marshalling per tick
-            r.pos += len(lists[-1])
-        self.batch.apply([r.state for r in work], lists, tile_amps=self.tile_amps, min_run=self.min_run,
-                         reorder=self.reorder)
+        for r in finishing:
+            norm_noalloc([r.state], self.norms[r.slot:r.slot + 1])
         ev = self.torch.cuda.Event()
         ev.record(self.stream)
         self.events[self.ticks] = ev
-        for r in work:
-            if r.pos >= len(r.gates):
-                r.done_tick = self.ticks
+        for r in finishing:
+            r.done_tick = self.ticks
         self.ticks += 1
         return True
 

@@ -86,3 +86,18 @@ def test_arrivals_join_while_others_run():
     assert all(r.admitted < long_req.finished for r in shorts)
     assert sum(r.finished < long_req.finished for r in shorts) >= len(shorts) // 2
     srv.close()
+
+
+def test_empty_circuit_retires_and_norms_match():
+    # A request with no gates finishes at the next tick with the norm of
+    # |0...0>; every served norm (written by the device into pinned memory, with
+    # no wait on the shared stream) equals qd_norm of the final state bitwise.
+    specs, reqs = make_requests(10, qps=2000.0, lo=1e3, hi=1e5, depth_lo=5, depth_hi=30, seed=34)
+    empty = qd().serve.ServeRequest(500, 0.001, [3, 2, 5], qd().GateList([]))
+    srv = qd().serve.Server("c128", quantum=4, keep_states=True)
+    rep = srv.run(reqs + [empty], realtime=True, timeout=60.0)
+    assert rep["requests"] == 11
+    assert empty.finished is not None and empty.norm == 1.0
+    for r in srv.finished:
+        assert r.norm == r.state.norm(), f"request {r.rid}"
+    srv.close()
