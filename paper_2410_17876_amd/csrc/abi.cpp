@@ -901,11 +901,7 @@ int build_round(qd_state* const* states, int32_t nstates, const BatchInput& in, 
         const size_t base = (out.blob.size() + 15) / 16 * 16;
         out.blob.resize(base + pp.blob.size());
         std::memcpy(out.blob.data() + base, pp.blob.data(), pp.blob.size());
-        TileGate* tg = reinterpret_cast<TileGate*>(out.blob.data() + base + f.gates_off);
-        for (int g = 0; g < f.ngates; ++g) {
-            tg[g].u_off += (uint32_t)base;
-            tg[g].bases_off += (uint32_t)base;
-        }
+        rebase_pass_blob(out.blob.data() + base, f, 0, (uint32_t)base);
         BatchItem it;
         std::memset(&it, 0, sizeof it);
         it.psi = reinterpret_cast<uint64_t>(states[i]->psi);

@@ -54,8 +54,42 @@ constexpr int32_t kDenseChain = 9;  // TileGate::kind of a chain; M2 = its lengt
 constexpr int kChainMaxM = 3;  // at 4, one gate's matrix (64 scalar registers in complex128) spills
 constexpr int kChainMaxLen = 16;
 
+// A register block: a run of uncontrolled gates whose targets all lie in a set T
+// of at most 3 tile qudits with at most kBlockMaxJ (complex64) or
+// kBlockMaxJ128 (complex128) amplitudes in the joint class over T. A thread reads
+// a joint class (the amplitudes that differ only in the T digits) from LDS
+// once, applies every gate of the block to its sub-classes in registers with
+// the single-gate arithmetic (dense rows as dense_row, phases and shifts as the
+// monomial update), and writes it back once: bitwise the gate-by-gate result,
+// with one LDS round trip and one barrier for the whole block. The joint index
+// runs over T in the block's shape order (dims ascending; ties by tile
+// position), first position least significant; TileGate::off holds the tile
+// offsets of the J joint members, one_mask the shape id (kBlockShapes), M2 the
+// number of gates and u_off their BlockGate records.
+constexpr int32_t kBlock = 10;      // TileGate::kind of a register block
+constexpr int kBlockMaxJ = 16;
+constexpr int kBlockMaxJ128 = 8;
+constexpr int kBlockMaxGates = 32;
+
+// Block shapes: the dims of T in joint order (1 pads), joint size at most 16.
+constexpr int kBlockShapeCount = 19;
+constexpr int kBlockShapes[kBlockShapeCount][3] = {
+    {2, 1, 1}, {3, 1, 1}, {4, 1, 1}, {5, 1, 1}, {6, 1, 1}, {7, 1, 1},
+    {2, 2, 1}, {2, 3, 1}, {2, 4, 1}, {2, 5, 1}, {2, 6, 1}, {2, 7, 1}, {3, 3, 1}, {3, 4, 1}, {3, 5, 1}, {4, 4, 1},
+    {2, 2, 2}, {2, 2, 3}, {2, 2, 4}};
+
+// One gate of a block: code = kind * 16 + p * 4 + q, p (and q) the joint
+// positions of its first (and second) target.
+enum BlockKind { kBlkDense1 = 0, kBlkDiag1 = 1, kBlkShift1 = 2, kBlkDense2 = 3 };
+struct BlockGate {
+    int32_t code;
+    uint32_t u_off;     // blob offset: dense: the M x M matrix; phase: one factor per local index
+    uint32_t one_mask;  // phase: bit a set if local index a keeps its amplitude (factor exactly 1)
+    int32_t shift;      // shift: |a> -> |a + shift mod d>
+};
+
 struct TileGate {
-    int32_t kind;        // kDense, kDensePair, kDenseChain, or kMonomial for monomial and diagonal gates
+    int32_t kind;        // kDense, kDensePair, kDenseChain, kBlock, or kMonomial for monomial and diagonal gates
     int32_t M;           // dense, chain: class size; pair: class size of the first gate; monomial: active entries
     int32_t M2;          // pair: class size of the second gate (its U follows the first's in the blob);
                          // chain: number of gates

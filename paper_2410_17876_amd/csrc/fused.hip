@@ -307,6 +307,200 @@ __device__ __forceinline__ void tile_chain(typename Cx<R>::T* tile, const TileGa
     });
 }
 
+// ---- register blocks (kBlock in fused.h) -------------------------------------------
+
+template <int D0, int D1, int D2>
+struct BlockShape {
+    static constexpr int L = D1 == 1 ? 1 : (D2 == 1 ? 2 : 3);  // qudits in the block
+    static constexpr int J = D0 * D1 * D2;                     // joint class size
+    static constexpr int d(int p) { return p == 0 ? D0 : (p == 1 ? D1 : D2); }
+    static constexpr int st(int p) { return p == 0 ? 1 : (p == 1 ? D0 : D0 * D1); }
+};
+
+// Largest class a block gate may have: its matrix is read into scalar registers
+// (4 M^2 of them in complex128, 2 M^2 in complex64).
+template <typename R>
+constexpr int block_max_m() {
+    return sizeof(R) == 8 ? 4 : 7;
+}
+
+// Joint index of member a of sub-class s of a one-qudit gate at position P (the
+// sub-class enumerates the other positions, lower ones least significant).
+template <class SH, int P>
+constexpr int blk_j1(int s, int a) {
+    return s % SH::st(P) + SH::st(P) * (a + SH::d(P) * (s / SH::st(P)));
+}
+
+// Joint index of member a = a_p + d(P) a_q of sub-class s of a two-qudit gate on
+// positions (P, Q); s is the digit of the remaining position (0 when there are two).
+template <class SH, int P, int Q>
+constexpr int blk_j2(int s, int a) {
+    return (SH::L == 3 ? s * SH::st(3 - P - Q) : 0) + (a % SH::d(P)) * SH::st(P) + (a / SH::d(P)) * SH::st(Q);
+}
+
+template <typename R, class SH, int P>
+__device__ __forceinline__ void blk_dense1(typename Cx<R>::T (&x)[SH::J], const typename Cx<R>::T* __restrict__ U) {
+    using T = typename Cx<R>::T;
+    constexpr int M = SH::d(P), NS = SH::J / M;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        T v[M];
+#pragma unroll
+        for (int a = 0; a < M; ++a) v[a] = x[blk_j1<SH, P>(s, a)];
+#pragma unroll
+        for (int r = 0; r < M; ++r) x[blk_j1<SH, P>(s, r)] = dense_row<R, M>(v, [&](int i) { return U[i]; }, r);
+    }
+}
+
+template <typename R, class SH, int P, int Q>
+__device__ __forceinline__ void blk_dense2(typename Cx<R>::T (&x)[SH::J], const typename Cx<R>::T* __restrict__ U) {
+    using T = typename Cx<R>::T;
+    constexpr int M = SH::d(P) * SH::d(Q), NS = SH::J / M;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        T v[M];
+#pragma unroll
+        for (int a = 0; a < M; ++a) v[a] = x[blk_j2<SH, P, Q>(s, a)];
+#pragma unroll
+        for (int r = 0; r < M; ++r) x[blk_j2<SH, P, Q>(s, r)] = dense_row<R, M>(v, [&](int i) { return U[i]; }, r);
+    }
+}
+
+// Phase gate: local index a of every sub-class scaled by lam[a] unless bit a of
+// one_mask says its factor is exactly 1 (as the monomial update).
+template <typename R, class SH, int P>
+__device__ __forceinline__ void blk_diag1(typename Cx<R>::T (&x)[SH::J], const typename Cx<R>::T* __restrict__ lam,
+                                          uint32_t one_mask) {
+    constexpr int M = SH::d(P), NS = SH::J / M;
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+        if ((one_mask >> a) & 1u) continue;  // uniform
+        const typename Cx<R>::T w = lam[a];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) x[blk_j1<SH, P>(s, a)] = scale_by(w, x[blk_j1<SH, P>(s, a)]);
+    }
+}
+
+// Cyclic shift |a> -> |a + S mod d> (factors exactly 1): pure moves.
+template <typename R, class SH, int P, int S>
+__device__ __forceinline__ void blk_shift(typename Cx<R>::T (&x)[SH::J]) {
+    using T = typename Cx<R>::T;
+    constexpr int M = SH::d(P), NS = SH::J / M;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        T v[M];
+#pragma unroll
+        for (int a = 0; a < M; ++a) v[a] = x[blk_j1<SH, P>(s, a)];
+#pragma unroll
+        for (int a = 0; a < M; ++a) x[blk_j1<SH, P>(s, (a + S) % M)] = v[a];
+    }
+}
+
+template <typename R, class SH, int P, int UF>
+__device__ __forceinline__ void blk_shift1(typename Cx<R>::T (&x)[UF][SH::J], int sh) {
+    constexpr int M = SH::d(P);
+    switch (sh) {  // uniform
+#define QD_SHIFT_CASE(k)                                                 \
+    case k:                                                              \
+        if constexpr ((k) < M) {                                         \
+            _Pragma("unroll") for (int u = 0; u < UF; ++u) blk_shift<R, SH, P, k>(x[u]); \
+        }                                                                \
+        break;
+        QD_SHIFT_CASE(1) QD_SHIFT_CASE(2) QD_SHIFT_CASE(3) QD_SHIFT_CASE(4) QD_SHIFT_CASE(5) QD_SHIFT_CASE(6)
+#undef QD_SHIFT_CASE
+        default: break;
+    }
+}
+
+// One gate of a block on UF joint classes.
+template <typename R, class SH, int UF>
+__device__ __forceinline__ void blk_gate(typename Cx<R>::T (&x)[UF][SH::J], const BlockGate* __restrict__ b,
+                                         const unsigned char* __restrict__ blob) {
+    using T = typename Cx<R>::T;
+    const T* __restrict__ U = reinterpret_cast<const T*>(blob + b->u_off);
+    constexpr int MM = block_max_m<R>();
+    switch (b->code) {
+#define QD_BLK1(p)                                                                          \
+    case kBlkDense1 * 16 + (p)*4:                                                           \
+        if constexpr ((p) < SH::L && SH::d(p) <= MM) {                                      \
+            _Pragma("unroll") for (int u = 0; u < UF; ++u) blk_dense1<R, SH, p>(x[u], U);   \
+        }                                                                                   \
+        break;                                                                              \
+    case kBlkDiag1 * 16 + (p)*4:                                                            \
+        if constexpr ((p) < SH::L) {                                                        \
+            const uint32_t om = b->one_mask;                                                \
+            _Pragma("unroll") for (int u = 0; u < UF; ++u) blk_diag1<R, SH, p>(x[u], U, om); \
+        }                                                                                   \
+        break;                                                                              \
+    case kBlkShift1 * 16 + (p)*4:                                                           \
+        if constexpr ((p) < SH::L) blk_shift1<R, SH, p, UF>(x, b->shift);                   \
+        break;
+        QD_BLK1(0) QD_BLK1(1) QD_BLK1(2)
+#undef QD_BLK1
+#define QD_BLK2(p, q)                                                                          \
+    case kBlkDense2 * 16 + (p)*4 + (q):                                                        \
+        if constexpr ((p) < SH::L && (q) < SH::L && SH::d(p) * SH::d(q) <= MM) {               \
+            _Pragma("unroll") for (int u = 0; u < UF; ++u) blk_dense2<R, SH, p, q>(x[u], U);   \
+        }                                                                                      \
+        break;
+        QD_BLK2(0, 1) QD_BLK2(1, 0) QD_BLK2(0, 2) QD_BLK2(2, 0) QD_BLK2(1, 2) QD_BLK2(2, 1)
+#undef QD_BLK2
+        default: break;
+    }
+}
+
+template <typename R, int D0, int D1, int D2, int BS>
+__device__ __forceinline__ void tile_block(typename Cx<R>::T* tile, const TileGate* __restrict__ G,
+                                           const unsigned char* __restrict__ blob, const uint16_t* bases,
+                                           const uint32_t (&pre)[kPre]) {
+    using T = typename Cx<R>::T;
+    using SH = BlockShape<D0, D1, D2>;
+    constexpr int J = SH::J;
+    constexpr int UF = J <= 4 ? 2 : 1;
+    uint32_t off[J];
+#pragma unroll
+    for (int a = 0; a < J; ++a) off[a] = G->off[a];
+    const BlockGate* __restrict__ bg = reinterpret_cast<const BlockGate*>(blob + G->u_off);
+    const int ng = G->M2;
+    for_classes<UF, BS>(G, bases, pre, [&](const uint32_t (&base)[UF], const bool (&ok)[UF]) {
+        T x[UF][J];
+#pragma unroll
+        for (int u = 0; u < UF; ++u)
+#pragma unroll
+            for (int a = 0; a < J; ++a) x[u][a] = ok[u] ? tile[base[u] + off[a]] : T{0, 0};
+#pragma unroll 1
+        for (int g = 0; g < ng; ++g) blk_gate<R, SH, UF>(x, bg + __builtin_amdgcn_readfirstlane(g), blob);
+#pragma unroll
+        for (int u = 0; u < UF; ++u) {
+            if (!ok[u]) continue;
+#pragma unroll
+            for (int a = 0; a < J; ++a) tile[base[u] + off[a]] = x[u][a];
+        }
+    });
+}
+
+// A block on its shape (kBlockShapes); complex128 joint classes stop at kBlockMaxJ128.
+template <typename R, int BS>
+__device__ __forceinline__ void tile_block_shape(typename Cx<R>::T* tile, const TileGate* __restrict__ G,
+                                                 const unsigned char* __restrict__ blob, const uint16_t* bases,
+                                                 const uint32_t (&pre)[kPre]) {
+    constexpr int JM = sizeof(R) == 8 ? kBlockMaxJ128 : kBlockMaxJ;
+    static_assert(kBlockShapeCount == 19, "a case per block shape");
+    switch (G->one_mask) {
+#define QD_SHAPE(id)                                                                                       \
+    case id:                                                                                               \
+        if constexpr (kBlockShapes[id][0] * kBlockShapes[id][1] * kBlockShapes[id][2] <= JM)               \
+            tile_block<R, kBlockShapes[id][0], kBlockShapes[id][1], kBlockShapes[id][2], BS>(tile, G, blob, \
+                                                                                             bases, pre);  \
+        break;
+        QD_SHAPE(0) QD_SHAPE(1) QD_SHAPE(2) QD_SHAPE(3) QD_SHAPE(4) QD_SHAPE(5) QD_SHAPE(6) QD_SHAPE(7) QD_SHAPE(8)
+        QD_SHAPE(9) QD_SHAPE(10) QD_SHAPE(11) QD_SHAPE(12) QD_SHAPE(13) QD_SHAPE(14) QD_SHAPE(15) QD_SHAPE(16)
+        QD_SHAPE(17) QD_SHAPE(18)
+#undef QD_SHAPE
+        default: break;
+    }
+}
+
 // First gate at or after g whose outer controls hold for this tile (uniform).
 __device__ __forceinline__ int next_live_gate(const TileGate* __restrict__ gates, int g, int ngates, uint64_t obase) {
     for (; g < ngates; ++g) {
@@ -330,7 +524,9 @@ __device__ __forceinline__ void apply_gates(typename Cx<R>::T* tile, I obase, in
         const TileGate* __restrict__ G = gates + __builtin_amdgcn_readfirstlane(g);
         const T* U = reinterpret_cast<const T*>(blob + G->u_off);
         const uint16_t* bases = reinterpret_cast<const uint16_t*>(blob + G->bases_off);
-        if (G->kind == kDensePair) {
+        if (G->kind == kBlock) {
+            tile_block_shape<R, BS>(tile, G, blob, bases, pre);
+        } else if (G->kind == kDensePair) {
             switch (G->M * 8 + G->M2) {
 #define QD_PAIR_CASE(m1, m2) \
     case m1 * 8 + m2: tile_pair<R, m1, m2, BS>(tile, G, U, bases, pre); break;

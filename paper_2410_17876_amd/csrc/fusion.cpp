@@ -36,6 +36,28 @@ bool same_classes(const CircuitGate& a, const CircuitGate& b) {
     return true;
 }
 
+// Largest dense class a register block takes (its matrix is read into scalar
+// registers) and the largest joint class, per precision.
+int block_max_m(int precision) { return precision == kC128 ? 4 : 7; }
+int block_max_j(int precision) { return precision == kC128 ? kBlockMaxJ128 : kBlockMaxJ; }
+
+// How a gate with this plan (k targets, m controls) enters a register block, or
+// -1: uncontrolled dense gates on one or two qudits with small classes, and
+// one-qudit phases and cyclic shifts (every factor exactly 1); *shift receives
+// the shift.
+int block_kind(const GatePlan& p, int k, int m, int precision, int* shift) {
+    if (m != 0 || k > 2) return -1;
+    if (p.category == kDense) return p.M <= block_max_m(precision) ? (k == 1 ? kBlkDense1 : kBlkDense2) : -1;
+    if (k != 1) return -1;
+    if (p.category == kDiagonal) return kBlkDiag1;
+    if (p.category != kMonomial || p.n_active != p.M) return -1;
+    const int sh = ((p.dst[0] - p.src[0]) % p.M + p.M) % p.M;
+    for (int j = 0; j < p.n_active; ++j)
+        if (!p.lam_one[j] || p.dst[j] != (p.src[j] + sh) % p.M) return -1;
+    if (shift) *shift = sh;
+    return kBlkShift1;
+}
+
 template <typename R>
 void put_complex(unsigned char* dst, double re, double im) {
     R v[2] = {static_cast<R>(re), static_cast<R>(im)};
@@ -157,10 +179,110 @@ int build_fused(const int32_t* dims, int n, int precision, const CircuitGate* ga
         return A.plan.category == kDense && B.plan.category == kDense && A.plan.M <= kChainMaxM &&
                same_classes(gates[A.gi], gates[B.gi]);
     };
-    GatePlan joint;  // geometry of a pair's joint class
+    GatePlan joint;  // geometry of a pair's or a block's joint class
+    const int jmax = block_max_j(precision);
+    auto in_block = [&](const Local& A) { return block_kind(A.plan, A.k, A.in_tile_controls + A.t.n_outer, precision,
+                                                            nullptr) >= 0; };
     for (size_t i = 0; i < locs.size(); ++i) {
         Local& A = locs[i];
         TileGate t = A.t;
+        // A register block: the longest run of block gates from here whose targets
+        // fit one joint class of at most 3 qudits and jmax amplitudes.
+        size_t blen = 0;
+        std::vector<int> T;  // tile-local qudits of the block
+        if (in_block(A)) {
+            uint64_t J = 1;
+            while (i + blen < locs.size() && blen < (size_t)kBlockMaxGates && in_block(locs[i + blen])) {
+                const Local& B = locs[i + blen];
+                std::vector<int> U = T;
+                uint64_t JU = J;
+                for (int l = 0; l < B.k; ++l)
+                    if (std::find(U.begin(), U.end(), B.lt[l]) == U.end()) {
+                        U.push_back(B.lt[l]);
+                        JU *= (uint64_t)tdims[B.lt[l]];
+                    }
+                if (U.size() > 3 || JU > (uint64_t)jmax) break;
+                T.swap(U);
+                J = JU;
+                ++blen;
+            }
+        }
+        if (blen >= 2) {
+            // Shape order: dims ascending, ties by tile position.
+            std::sort(T.begin(), T.end(), [&](int a, int b) {
+                return tdims[a] != tdims[b] ? tdims[a] < tdims[b] : a < b;
+            });
+            int shape = -1;
+            for (int sh = 0; sh < kBlockShapeCount && shape < 0; ++sh) {
+                bool same = true;
+                for (int p = 0; p < 3; ++p)
+                    same = same && kBlockShapes[sh][p] == (p < (int)T.size() ? tdims[T[p]] : 1);
+                if (same) shape = sh;
+            }
+            if (shape < 0) {
+                *err = "internal: register block without a shape";
+                return QD_ERR_NOT_SUPPORTED;
+            }
+            int32_t jt[QD_MAX_TARGETS];
+            int J = 1;
+            for (size_t p = 0; p < T.size(); ++p) {
+                jt[p] = T[p];
+                J *= tdims[T[p]];
+            }
+            std::vector<double> eye(2 * (size_t)J * J, 0.0);
+            for (int a = 0; a < J; ++a) eye[2 * ((size_t)a * J + a)] = 1.0;
+            int rc = plan_gate(tdims, nS, jt, (int)T.size(), nullptr, nullptr, 0, eye.data(), &joint, err);
+            if (rc) return rc;
+            put_classes(t, joint);
+            t.kind = kBlock;
+            t.M = J;
+            t.M2 = (int32_t)blen;
+            t.one_mask = (uint32_t)shape;
+            t.n_outer = 0;
+            for (int a = 0; a < J; ++a) t.off[a] = (uint32_t)joint.off[a];
+            t.u_off = (uint32_t)udata.size();
+            udata.resize(align_up(udata.size() + blen * sizeof(BlockGate), 16));
+            for (size_t j = 0; j < blen; ++j) {
+                const Local& B = locs[i + j];
+                const GatePlan& gpl = B.plan;
+                BlockGate bg;
+                std::memset(&bg, 0, sizeof bg);
+                int sh = 0;
+                const int kind = block_kind(gpl, B.k, 0, precision, &sh);
+                auto pos = [&](int q) { return (int)(std::find(T.begin(), T.end(), q) - T.begin()); };
+                bg.code = kind * 16 + pos(B.lt[0]) * 4 + (B.k > 1 ? pos(B.lt[1]) : 0);
+                bg.u_off = (uint32_t)udata.size();
+                if (kind == kBlkDense1 || kind == kBlkDense2) {
+                    put_u(gates[B.gi].U, gpl.M);
+                } else if (kind == kBlkDiag1) {
+                    // one factor per local index; identity columns and factors of exactly 1 are kept
+                    std::vector<double> lam(2 * (size_t)gpl.M, 0.0);
+                    uint32_t om = (1u << gpl.M) - 1;
+                    for (int a = 0; a < gpl.M; ++a) lam[2 * a] = 1.0;
+                    for (int jj = 0; jj < gpl.n_active; ++jj) {
+                        const int a = gpl.src[jj];
+                        lam[2 * a] = gpl.lam[2 * jj];
+                        lam[2 * a + 1] = gpl.lam[2 * jj + 1];
+                        if (!gpl.lam_one[jj]) om &= ~(1u << a);
+                    }
+                    const size_t at = udata.size();
+                    udata.resize(at + (size_t)gpl.M * ab);
+                    for (int a = 0; a < gpl.M; ++a) {
+                        if (precision == kC128) put_complex<double>(udata.data() + at + a * ab, lam[2 * a], lam[2 * a + 1]);
+                        else put_complex<float>(udata.data() + at + a * ab, lam[2 * a], lam[2 * a + 1]);
+                    }
+                    bg.one_mask = om;
+                } else {
+                    bg.shift = sh;
+                }
+                udata.resize(align_up(udata.size(), 16));
+                std::memcpy(udata.data() + t.u_off + j * sizeof(BlockGate), &bg, sizeof bg);
+            }
+            i += blen - 1;
+            udata.resize(align_up(udata.size(), 16));
+            tg.push_back(t);
+            continue;
+        }
         size_t len = 1;
         while (i + len < locs.size() && len < (size_t)kChainMaxLen && chains_with(A, locs[i + len])) ++len;
         if (len > 1) {
@@ -227,16 +349,15 @@ int build_fused(const int32_t* dims, int n, int precision, const CircuitGate* ga
     // relative to the start of the gate data; rebase them to the blob start.
     f.gates_off = 0;
     const size_t data_off = align_up(sizeof(TileGate) * tg.size(), 16);
-    for (TileGate& t : tg) {
-        t.u_off += (uint32_t)data_off;
-        t.bases_off += (uint32_t)data_off;
-    }
     f.run_off_off = align_up(data_off + udata.size(), 16);
     const bool narrow = D < (1ull << 31);
     const size_t ob = narrow ? 4 : 8;
     out->blob.assign(f.run_off_off + R * ob, 0);
     if (!tg.empty()) std::memcpy(out->blob.data(), tg.data(), sizeof(TileGate) * tg.size());
     if (!udata.empty()) std::memcpy(out->blob.data() + data_off, udata.data(), udata.size());
+    // Offsets so far count from the start of the gate data; make them count
+    // from the start of the blob.
+    rebase_pass_blob(out->blob.data(), f, (uint32_t)data_off, (uint32_t)data_off);
     // Run r enumerates the digits of S above the low block, in increasing qudit order.
     for (uint64_t r = 0; r < R; ++r) {
         uint64_t rest = r, off = 0;
@@ -256,6 +377,18 @@ int build_fused(const int32_t* dims, int n, int precision, const CircuitGate* ga
     out->fused = true;
     out->gates = idx;
     return QD_OK;
+}
+
+void rebase_pass_blob(unsigned char* blob, const FusedLaunch& f, uint32_t frame, uint32_t delta) {
+    TileGate* tg = reinterpret_cast<TileGate*>(blob + f.gates_off);
+    for (int g = 0; g < f.ngates; ++g) {
+        if (tg[g].kind == kBlock) {
+            BlockGate* bg = reinterpret_cast<BlockGate*>(blob + frame + tg[g].u_off);
+            for (int j = 0; j < tg[g].M2; ++j) bg[j].u_off += delta;
+        }
+        tg[g].u_off += delta;
+        tg[g].bases_off += delta;
+    }
 }
 
 int plan_circuit(const int32_t* dims, int n, int precision, const CircuitGate* gates, int count,
@@ -279,8 +412,10 @@ int plan_circuit(const int32_t* dims, int n, int precision, const CircuitGate* g
     // their fusability, device-data bound and qudit masks.
     struct Info {
         bool skip, can, chain;  // chain: dense with a class small enough for a chain
+        bool block;             // may join a register block
         size_t bytes;
         uint64_t tmask, cmask;
+        uint64_t M;
     };
     std::vector<Info> info(count);
     {
@@ -293,6 +428,8 @@ int plan_circuit(const int32_t* dims, int n, int precision, const CircuitGate* g
             f.skip = gp->category == kIdentity;
             f.can = opt.fuse && fusable(*gp, g.m);
             f.chain = gp->category == kDense && gp->M <= kChainMaxM;
+            f.block = block_kind(*gp, g.k, g.m, precision, nullptr) >= 0;
+            f.M = (uint64_t)gp->M;
             f.bytes = sizeof(TileGate) + (size_t)tile_bound + (size_t)gp->M * gp->M * 16 + 64;
             f.tmask = f.cmask = 0;
             for (int l = 0; l < g.k; ++l) f.tmask |= 1ull << g.targets[l];
@@ -378,6 +515,42 @@ int plan_circuit(const int32_t* dims, int n, int precision, const CircuitGate* g
                         if ((f.tmask & (h.tmask | h.cmask)) || (f.cmask & h.tmask)) break;
                     }
                 seq.insert(seq.begin() + (std::ptrdiff_t)at, gi);
+            }
+            cur.swap(seq);
+            // Then gather register blocks: a block gate takes every later block gate
+            // whose targets still fit its joint class (at most 3 qudits and
+            // block_max_j amplitudes) and that commutes with every gate it moves
+            // ahead of (block gates have no controls, so: its targets meet none of
+            // their targets or controls).
+            const uint64_t jmax = (uint64_t)block_max_j(precision);
+            std::vector<char> used(cur.size(), 0);
+            seq.clear();
+            for (size_t a = 0; a < cur.size(); ++a) {
+                if (used[a]) continue;
+                used[a] = 1;
+                seq.push_back(cur[a]);
+                const Info& f = info[cur[a]];
+                if (!f.block) continue;
+                uint64_t T = f.tmask, passA = 0;
+                for (size_t b = a + 1; b < cur.size(); ++b) {
+                    if (used[b]) continue;
+                    const Info& h = info[cur[b]];
+                    const uint64_t U = T | h.tmask;
+                    uint64_t J = 1;
+                    int nq = 0;
+                    for (int q = 0; q < n; ++q)
+                        if ((U >> q) & 1u) {
+                            J *= (uint64_t)dims[q];
+                            ++nq;
+                        }
+                    if (h.block && nq <= 3 && J <= jmax && !(h.tmask & passA)) {
+                        used[b] = 1;
+                        seq.push_back(cur[b]);
+                        T = U;
+                    } else {
+                        passA |= h.tmask | h.cmask;
+                    }
+                }
             }
             cur.swap(seq);
         }

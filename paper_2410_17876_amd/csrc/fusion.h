@@ -36,6 +36,12 @@ struct PassPlan {
     std::vector<unsigned char> blob;  // fused passes: device data, built for one precision
 };
 
+// Add `delta` to every offset a fused pass's device data holds (descriptor fields
+// and register-block records). The offsets count from blob + frame before the
+// call (so the records sit at blob + frame + offset), e.g. the pass's own blob
+// (frame 0) copied `delta` bytes into a larger buffer.
+void rebase_pass_blob(unsigned char* blob, const FusedLaunch& f, uint32_t frame, uint32_t delta);
+
 int plan_circuit(const int32_t* dims, int n, int precision, const CircuitGate* gates, int count,
                  const CircuitOptions& opt, std::vector<PassPlan>& out, std::string* err);
 

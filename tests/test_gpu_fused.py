@@ -284,3 +284,68 @@ def test_long_passes_with_large_tiles():
     b = q.State(dims, "c64", init=None).set_amplitudes(psi0)
     b.run(gates)
     assert np.array_equal(a.amplitudes(), b.amplitudes())
+
+
+def block_shape_gates(rng, dims, T, count, max_m):
+    # uncontrolled gates on the qudits T (a register block's joint class):
+    # dense on one or two of them (classes up to max_m), phases with some
+    # factors exactly 1, and cyclic shifts by every amount
+    out = []
+    while len(out) < count:
+        r = rng.random()
+        if r < 0.4 or len(T) == 1:
+            q = int(rng.choice(T))
+            d = dims[q]
+            kind = int(rng.integers(4))
+            if kind == 0 and d <= max_m:
+                out.append(Gate((q,), haar(d, rng)))
+            elif kind == 1:
+                out.append(Gate((q,), shift(d, int(rng.integers(1, d)))))
+            elif kind == 2:
+                out.append(Gate((q,), np.diag(np.where(rng.random(d) < 0.3, 1.0, np.exp(2j * np.pi * rng.random(d))))))
+            else:
+                out.append(Gate((q,), clock(d)))
+        else:
+            a, b = (int(x) for x in rng.choice(T, 2, replace=False))
+            if dims[a] * dims[b] <= max_m:
+                out.append(Gate((a, b), haar(dims[a] * dims[b], rng)))
+    return out
+
+
+# Every register-block shape (joint-class dims in ascending order), each on
+# qudits spread over a register with other dims around them.
+BLOCK_SHAPES = [(2,), (3,), (4,), (5,), (6,), (7,), (2, 2), (2, 3), (2, 4), (2, 5), (2, 6), (2, 7), (3, 3), (3, 4),
+                (3, 5), (4, 4), (2, 2, 2), (2, 2, 3), (2, 2, 4)]
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_register_blocks_every_shape_bitwise(precision):
+    # Register blocks apply runs of uncontrolled gates in registers: the fused
+    # result equals one sweep per gate bit for bit (in the given order, and with
+    # look-ahead in the planned order) and the oracle within the tolerances.
+    q = qd()
+    max_m = 4 if precision == "c128" else 7
+    rng = np.random.default_rng(2024)
+    for shape in BLOCK_SHAPES:
+        # the block's qudits at positions 1, 3 (and 5) among qubits and a qutrit
+        dims = [2, shape[0], 3, shape[1] if len(shape) > 1 else 2, 2, shape[2] if len(shape) > 2 else 3, 2]
+        T = [1, 3, 5][:len(shape)]
+        gates = block_shape_gates(rng, dims, T, 24, max_m)
+        # a controlled gate in the middle ends one block and starts another
+        gates.insert(12, Gate((T[0],), shift(dims[T[0]]), (6,), (1,)))
+        psi0 = rand_state(rng, math.prod(dims))
+        for reorder in (0, 32):
+            passes, order = q.circuit_plan(dims, gates, precision, tile_amps=1024, min_run=2, reorder=reorder,
+                                           with_order=True)
+            a = q.State(dims, precision, init=None).set_amplitudes(psi0)
+            a.run_circuit(gates, tile_amps=1024, min_run=2, reorder=reorder)
+            c = q.State(dims, precision, init=None).set_amplitudes(psi0)
+            c.run([gates[i] for i in order])
+            assert np.array_equal(a.amplitudes(), c.amplitudes()), f"shape {shape}, reorder {reorder}"
+            ref = psi0.copy() if precision == "c128" else (psi0.real.astype(np.float32).astype(np.float64) +
+                                                           1j * psi0.imag.astype(np.float32).astype(np.float64))
+            for g in gates:
+                oracle.apply_gate(dims, ref, g)
+            assert_close(a.amplitudes(), ref, precision, f"blocks {shape} reorder {reorder}")
+            a.close()
+            c.close()
