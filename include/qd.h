@@ -327,10 +327,12 @@ int qd_batch_plan_run(qd_batch_plan* plan, int32_t use_graph);
 /* Wait for the plan's stream, then free the plan (not the states). */
 int qd_batch_plan_destroy(qd_batch_plan* plan);
 
-/* ||psi||_2 = sqrt(sum_j |a_j|^2), summed in FP64 on the device in a fixed
- * order (the same result for the same state, run after run). Synchronous: it
- * waits for the state's stream. The device's reduction scratch is shared by all
- * states and serialised by a lock. */
+/* ||psi||_2 = sqrt(sum_j |a_j|^2) over the amplitudes a_j of the basis states
+ * |j> (Sec. 2 sets up the statevector as these amplitudes; every gate there is
+ * a unitary, so the norm of a normalised input stays 1 and is the check of a
+ * run). Summed in FP64 on the device in a fixed order (the same result for the
+ * same state, run after run). Synchronous: it waits for the state's stream. The
+ * device's reduction scratch is shared by all states and serialised by a lock. */
 int qd_norm(const qd_state* s, double* out);
 
 /* ---- the norm without allocation --------------------------------------------------- */

@@ -23,9 +23,10 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_build.LIB):
+        path = os.environ.get("QD_ORACLE_LIB", _build.LIB)  # e.g. the sanitizer build
+        if path == _build.LIB and not os.path.exists(path):
             _build.build()
-        L = C.CDLL(_build.LIB)
+        L = C.CDLL(path)
         i32p = np.ctypeslib.ndpointer(np.int32, flags="C")
         i64p = np.ctypeslib.ndpointer(np.int64, flags="C")
         f64p = np.ctypeslib.ndpointer(np.float64, flags="C")

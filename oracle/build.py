@@ -15,15 +15,24 @@ SRC = os.path.join(HERE, "qd_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 
-def build(verbose: bool = False) -> str:
-    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-fPIC", "-shared",
-           "-fopenmp", "-Wall", "-Wextra", "-o", LIB + ".tmp", SRC, "-lm"]
+# Built with AddressSanitizer and UndefinedBehaviorSanitizer (and no OpenMP, whose
+# runtime the sanitizers do not follow) when the oracle itself is under test:
+# load it with QD_ORACLE_LIB=<path> and gcc's libasan/libubsan preloaded.
+LIB_SANITIZED = os.path.join(HERE, "liboracle_san.so")
+
+
+def build(verbose: bool = False, sanitize: bool = False) -> str:
+    out = LIB_SANITIZED if sanitize else LIB
+    flags = (["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+              "-fno-sanitize-recover=undefined", "-Wno-unknown-pragmas"] if sanitize else ["-O2", "-fopenmp"])
+    cmd = ["gcc", *flags, "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-fPIC", "-shared",
+           "-Wall", "-Wextra", "-o", out + ".tmp", SRC, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(out + ".tmp", out)
+    return out
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, sanitize="--sanitize" in sys.argv))

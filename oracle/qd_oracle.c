@@ -48,7 +48,6 @@
  * 0 on success and a negative value on invalid arguments.
  */
 #include <math.h>
-#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>

@@ -15,7 +15,8 @@ from typing import Optional, Sequence
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libqd.so")
+# QD_LIBQD selects another build of the same library (the host-sanitizer build)
+LIB_PATH = os.environ.get("QD_LIBQD", os.path.join(HERE, "libqd.so"))
 
 QD_C64, QD_C128 = 1, 2
 QD_DEVICE, QD_HOST = 0, 1

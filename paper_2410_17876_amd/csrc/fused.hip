@@ -57,12 +57,13 @@ __device__ __forceinline__ void dense_classes(typename Cx<R>::T* tile, const Til
                                               const typename Cx<R>::T* __restrict__ U, const uint32_t (&off)[M],
                                               const uint32_t (&base)[UF], const bool (&ok)[UF]) {
     using T = typename Cx<R>::T;
+    // Loads are unconditional: a class past the end has a clamped, valid base
+    // (for_classes), and only the stores below are predicated.
     T x[UF][M];
 #pragma unroll
     for (int u = 0; u < UF; ++u)
 #pragma unroll
-        for (int a = 0; a < M; ++a)
-            if (ok[u]) x[u][a] = tile[base[u] + off[a]];
+        for (int a = 0; a < M; ++a) x[u][a] = tile[base[u] + off[a]];
     if constexpr (M <= 2) {
 #pragma unroll
         for (int u = 0; u < UF; ++u) {
@@ -115,8 +116,7 @@ __device__ __forceinline__ void mono_classes(typename Cx<R>::T* tile, const type
 #pragma unroll
     for (int u = 0; u < UF; ++u)
 #pragma unroll
-        for (int i = 0; i < A; ++i)
-            if (ok[u]) x[u][i] = tile[base[u] + src[i]];
+        for (int i = 0; i < A; ++i) x[u][i] = tile[base[u] + src[i]];  // clamped bases: unconditional
 #pragma unroll
     for (int u = 0; u < UF; ++u) {
         if (!ok[u]) continue;
@@ -203,8 +203,7 @@ __device__ __forceinline__ void pair_classes(typename Cx<R>::T* tile, const Tile
 #pragma unroll
     for (int u = 0; u < UF; ++u)
 #pragma unroll
-        for (int a = 0; a < J; ++a)
-            if (ok[u]) x[u][a] = tile[base[u] + off[a]];
+        for (int a = 0; a < J; ++a) x[u][a] = tile[base[u] + off[a]];  // clamped bases: unconditional
     // For each output row a1 of the first gate: y[b] = row a1 of U1 on sub-class
     // b (x[M1 b .. M1 b + M1)), which is exactly the input of the second gate's
     // sub-class a1; its rows go straight to LDS.
@@ -271,7 +270,7 @@ __device__ __forceinline__ void chain_classes(typename Cx<R>::T* tile, const typ
 #pragma unroll
     for (int u = 0; u < UF; ++u)
 #pragma unroll
-        for (int a = 0; a < M; ++a) x[u][a] = ok[u] ? tile[base[u] + off[a]] : T{0, 0};
+        for (int a = 0; a < M; ++a) x[u][a] = tile[base[u] + off[a]];  // clamped bases: unconditional
 #pragma unroll 1
     for (int g = 0; g + 1 < n; ++g) {
         const T* __restrict__ Ug = U + g * M * M;
@@ -467,7 +466,7 @@ __device__ __forceinline__ void tile_block(typename Cx<R>::T* tile, const TileGa
 #pragma unroll
         for (int u = 0; u < UF; ++u)
 #pragma unroll
-            for (int a = 0; a < J; ++a) x[u][a] = ok[u] ? tile[base[u] + off[a]] : T{0, 0};
+            for (int a = 0; a < J; ++a) x[u][a] = tile[base[u] + off[a]];  // clamped bases: unconditional
 #pragma unroll 1
         for (int g = 0; g < ng; ++g) blk_gate<R, SH, UF>(x, bg + __builtin_amdgcn_readfirstlane(g), blob);
 #pragma unroll
@@ -596,9 +595,13 @@ __device__ __forceinline__ bool chunk_at(const TileGeom& a, const I* __restrict_
     return in && e < a.L;
 }
 
-// Whole tile <-> HBM. Loads are unconditional (chunk_at clamps), so the
-// compiler issues a wavefront's U4 loads back to back with no wait between them:
-// 256 bytes per lane in flight, a whole 64 KB tile per 256-thread workgroup.
+// Whole tile <-> HBM. Nothing is predicated: a lane past the end of a run or of
+// the tile gets the clamped last element (chunk_at), whose address in HBM and
+// place in the tile belong together, so it loads, writes to LDS and stores back
+// exactly what the lane that owns that element does (the same value to the same
+// address). The compiler issues a wavefront's U4 loads back to back with no wait
+// between them: 256 bytes per lane in flight, a whole 64 KB tile per 256-thread
+// workgroup.
 template <typename T, typename I, bool LOAD, int BS>
 __device__ __forceinline__ void move_tile(T* __restrict__ psi, T* tile, I obase, const TileGeom& a,
                                           const I* __restrict__ run_off) {
@@ -610,19 +613,16 @@ __device__ __forceinline__ void move_tile(T* __restrict__ psi, T* tile, I obase,
         T v[U4];
         uint32_t t_at[U4];
         I g_off[U4];
-        bool ok[U4];
 #pragma unroll
-        for (int u = 0; u < U4; ++u) ok[u] = chunk_at<I>(a, run_off, k0 + u * nw, lane, &t_at[u], &g_off[u]);
+        for (int u = 0; u < U4; ++u) (void)chunk_at<I>(a, run_off, k0 + u * nw, lane, &t_at[u], &g_off[u]);
         if (LOAD) {
 #pragma unroll
             for (int u = 0; u < U4; ++u) v[u] = ld_stream(psi + obase + g_off[u]);
 #pragma unroll
-            for (int u = 0; u < U4; ++u)
-                if (ok[u]) tile[t_at[u]] = v[u];
+            for (int u = 0; u < U4; ++u) tile[t_at[u]] = v[u];
         } else {
 #pragma unroll
-            for (int u = 0; u < U4; ++u)
-                if (ok[u]) st_stream(psi + obase + g_off[u], tile[t_at[u]]);
+            for (int u = 0; u < U4; ++u) st_stream(psi + obase + g_off[u], tile[t_at[u]]);
         }
     }
 }
