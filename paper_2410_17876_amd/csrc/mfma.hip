@@ -173,13 +173,45 @@ __global__ __launch_bounds__(kMfmaBlock) void block_mfma(typename Cx<R>::T* __re
         *r = rmap[real ? low + ord.inner * (int)hi : 0];  // index < M for real elements
         return real && *c < ncols;
     };
+    // A thread's elements are the same in every tile (e = thread + i * block).
+    // For blocks of at most 32 members their (local index, class) pairs and
+    // member offsets are decoded once, here (only the class count of the last
+    // tile can exclude more of them); the larger shapes need those registers
+    // for their fragments and decode per use.
+    constexpr bool PRE = MP == 32;
+    int er[PRE ? EPT : 1], ec[PRE ? EPT : 1];
+    I eoff[PRE ? EPT : 1];
+    if constexpr (PRE) {
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            int r = 0, c = 0;
+            const bool real = element(threadIdx.x + i * kMfmaBlock, nt, &r, &c);
+            er[i] = real ? r : 0;
+            ec[i] = real ? c : S::NT;  // S::NT: never below a tile's class count
+            eoff[i] = offs[er[i]];
+        }
+    }
+    // Element i of this thread in a tile of ncols classes: false if it does not exist.
+    auto elem = [&](int i, int ncols, int* r, int* c, I* o) -> bool {
+        if constexpr (PRE) {
+            *r = er[i];
+            *c = ec[i];
+            *o = eoff[i];
+            return ec[i] < ncols;
+        } else {
+            const bool ok = element(threadIdx.x + i * kMfmaBlock, ncols, r, c);
+            *o = offs[ok ? *r : 0];
+            return ok;
+        }
+    };
     auto gather = [&](T (&v)[EPT], int buf, int ncols) {
         I addr[EPT];
 #pragma unroll
         for (int i = 0; i < EPT; ++i) {
             int r = 0, c = 0;
-            const bool ok = element(threadIdx.x + i * kMfmaBlock, ncols, &r, &c);
-            addr[i] = bases[buf][ok ? c : 0] + offs[ok ? r : 0];
+            I o = 0;
+            const bool ok = elem(i, ncols, &r, &c, &o);
+            addr[i] = bases[buf][ok ? c : 0] + (ok ? o : offs[0]);
         }
 #pragma unroll
         for (int i = 0; i < EPT; ++i) v[i] = ld_stream(psi + addr[i]);
@@ -188,7 +220,8 @@ __global__ __launch_bounds__(kMfmaBlock) void block_mfma(typename Cx<R>::T* __re
 #pragma unroll
         for (int i = 0; i < EPT; ++i) {
             int r = 0, c = 0;
-            if (element(threadIdx.x + i * kMfmaBlock, ncols, &r, &c)) {
+            I o = 0;
+            if (elem(i, ncols, &r, &c, &o)) {
                 Bs[r][c] = v[i].x;
                 Bs[MP + r][c] = v[i].y;
             }
@@ -296,13 +329,15 @@ __global__ __launch_bounds__(kMfmaBlock) void block_mfma(typename Cx<R>::T* __re
                     Bs[16 * rb + 4 * r + (lane >> 4)][16 * (CB * cb + c) + (lane & 15)] = acc[c][r];
         }
         __syncthreads();
-        for (int e = threadIdx.x; e < MN; e += kMfmaBlock) {
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
             int r = 0, c = 0;
-            if (element(e, ncols, &r, &c)) {
+            I o = 0;
+            if (elem(i, ncols, &r, &c, &o)) {
                 T y;
                 y.x = Bs[r][c];
                 y.y = Bs[MP + r][c];
-                st_stream(psi + bases[cur][c] + offs[r], y);
+                st_stream(psi + bases[cur][c] + o, y);
             }
         }
         __syncthreads();  // Bs free
