@@ -422,14 +422,14 @@ def run_sparse_ghz(qd, reps=3):
     qudit controlled on q0 = v), from |0...0>."""
     out = {}
     for d, n in GHZ_REGISTERS + GHZ_WIDE_REGISTERS:
-        gates = qd.GateList(ghz_gates(d, n)).gates
+        gl = qd.GateList(ghz_gates(d, n))  # marshalled once, outside the timed region
+        gates = gl.gates
         best = None
         for rep in range(reps + 1):  # the first build warms up
             st = qd.SparseState([d] * n)
             torch_sync()
             t0 = time.perf_counter()
-            for g in gates:
-                st.apply_gate(g)
+            st.run(gl)  # qd_sparse_apply_circuit
             nnz = st.nnz()  # waits for the state's stream
             dt = time.perf_counter() - t0
             words = st.words
@@ -442,8 +442,8 @@ def run_sparse_ghz(qd, reps=3):
     return {"workload": "GHZ_d from |0...0> on 62 qubits, 39 qutrits, 31 ququads, 27 ququints (the paper's largest), "
                         "and past 2^64: 100 qubits, 63 qutrits, 50 ququads, 43 ququints, 45 qudits of dim 7 "
                         "(sparse, complex128)",
-            "path": "qd_sparse_apply_gate: one workgroup per gate (group by class in LDS, U x per class, keep "
-                    "nonzeros, order by rank), enqueued with no host synchronisation; time = first gate to the "
+            "path": "qd_sparse_apply_circuit: one workgroup per gate (group by class in LDS, U x per class, keep "
+                    "nonzeros, order by rank), enqueued with no host synchronisation; time = the call to the "
                     "entry count read back",
             "registers": out}
 

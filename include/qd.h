@@ -45,6 +45,7 @@ extern "C" {
 #endif
 
 typedef struct qd_state qd_state;
+typedef struct qd_gate_desc qd_gate_desc; /* one gate of a gate list (defined below) */
 
 enum qd_precision { QD_C64 = 1, QD_C128 = 2 };
 
@@ -176,14 +177,14 @@ int qd_apply_gate_masked(qd_state* s, const int32_t* targets, int32_t k, const i
                          const uint32_t* value_masks, int32_t m, const double* U);
 
 /* One gate of a gate list: the arguments of qd_apply_gate. */
-typedef struct {
+struct qd_gate_desc {
     const int32_t* targets;
     int32_t k;
     const int32_t* controls;
     const int32_t* values;
     int32_t m;
     const double* U;
-} qd_gate_desc;
+};
 
 typedef struct {
     int32_t fuse;         /* 1 (default when opts is null): LDS-staged fusion of consecutive gates;
@@ -271,6 +272,12 @@ int qd_sparse_set_stream(qd_sparse* s, void* hip_stream);
  * result count back once. */
 int qd_sparse_apply_gate(qd_sparse* s, const int32_t* targets, int32_t k, const int32_t* controls,
                          const int32_t* values, int32_t m, const double* U);
+
+/* Apply gates[0..count-1] in order (each as qd_sparse_apply_gate). Every gate is
+ * validated before any work is enqueued, so an invalid gate leaves the state
+ * unchanged; a device error met part way may leave the result of a prefix of
+ * the list. */
+int qd_sparse_apply_circuit(qd_sparse* s, const qd_gate_desc* gates, int32_t count);
 
 /* Number of stored (nonzero) amplitudes. Waits for the state's stream. */
 int qd_sparse_nnz(qd_sparse* s, uint64_t* nnz);

@@ -80,6 +80,7 @@ def _load() -> C.CDLL:
         "qd_sparse_destroy": [vp],
         "qd_sparse_set_stream": [vp, vp],
         "qd_sparse_apply_gate": [vp, i32p, C.c_int32, i32p, i32p, C.c_int32, f64p],
+        "qd_sparse_apply_circuit": [vp, C.POINTER(GateDesc), C.c_int32],
         "qd_sparse_nnz": [vp, u64p],
         "qd_sparse_get": [vp, u64p, f64p, C.c_uint64],
         "qd_sparse_get_wide": [vp, u64p, f64p, C.c_uint64],
@@ -418,6 +419,12 @@ class SparseState:
 
     def apply_gate(self, g) -> "SparseState":
         return self.apply(g.targets, g.U, g.controls, g.values)
+
+    def run(self, gates) -> "SparseState":
+        """Apply a gate list in one call (qd_sparse_apply_circuit)."""
+        gl = gates if isinstance(gates, GateList) else GateList(gates)
+        check(lib.qd_sparse_apply_circuit(self._h, gl.descs, len(gl)))
+        return self
 
     def nnz(self) -> int:
         out = C.c_uint64()

@@ -545,14 +545,17 @@ int qd_sparse_set_stream(qd_sparse* s, void* hip_stream) {
     return QD_OK;
 }
 
-int qd_sparse_apply_gate(qd_sparse* s, const int32_t* targets, int32_t k, const int32_t* controls,
-                         const int32_t* values, int32_t m, const double* U) {
-    if (!s) return set_err(QD_ERR_INVALID_ARGUMENT, "state is null");
+namespace {
+
+// Validate a gate on a sparse register and build its kernel form (*cols_single:
+// every column of U has at most one nonzero).
+int sparse_gate_of(const qd_sparse* s, const int32_t* targets, int32_t k, const int32_t* controls,
+                   const int32_t* values, int32_t m, const double* U, qd::SparseGate* out, bool* cols_single) {
     std::string err;
     int rc = check_gate_shape(s->dims, s->n, targets, k, controls, values, m, &err);
     if (rc) return set_err(rc, err);
     if (!U) return set_err(QD_ERR_INVALID_ARGUMENT, "U is null");
-    qd::SparseGate g;
+    qd::SparseGate& g = *out;
     std::memset(&g, 0, sizeof g);
     g.W = s->d.W;
     g.k = k;
@@ -580,18 +583,55 @@ int qd_sparse_apply_gate(qd_sparse* s, const int32_t* targets, int32_t k, const 
     }
     // Every column with at most one nonzero: each entry feeds at most one result,
     // so the gate cannot raise the entry count.
-    bool cols_single = true;
-    for (int a = 0; a < g.M && cols_single; ++a) {
+    *cols_single = true;
+    for (int a = 0; a < g.M && *cols_single; ++a) {
         int nz = 0;
         for (int r = 0; r < g.M; ++r) nz += (U[2 * (r * g.M + a)] != 0.0 || U[2 * (r * g.M + a) + 1] != 0.0);
-        cols_single = nz <= 1;
+        *cols_single = nz <= 1;
     }
-    rc = sparse_device(s);
-    if (rc) return rc;
+    return QD_OK;
+}
+
+int sparse_enqueue(qd_sparse* s, const qd::SparseGate& g, const double* U, bool cols_single) {
     hipError_t e = qd::sparse_apply(s->d, g, U, cols_single);
     if (e == hipErrorNotSupported)
         return set_err(QD_ERR_NOT_SUPPORTED, "sparse state too large: stored entries x class size must stay below 2^31");
     if (e != hipSuccess) return sparse_hip_err(e, "sparse gate");
+    return QD_OK;
+}
+
+}  // namespace
+
+int qd_sparse_apply_gate(qd_sparse* s, const int32_t* targets, int32_t k, const int32_t* controls,
+                         const int32_t* values, int32_t m, const double* U) {
+    if (!s) return set_err(QD_ERR_INVALID_ARGUMENT, "state is null");
+    qd::SparseGate g;
+    bool cols_single = false;
+    int rc = sparse_gate_of(s, targets, k, controls, values, m, U, &g, &cols_single);
+    if (rc) return rc;
+    rc = sparse_device(s);
+    if (rc) return rc;
+    return sparse_enqueue(s, g, U, cols_single);
+}
+
+int qd_sparse_apply_circuit(qd_sparse* s, const qd_gate_desc* gates, int32_t count) {
+    if (!s) return set_err(QD_ERR_INVALID_ARGUMENT, "state is null");
+    if (count < 0 || (count > 0 && !gates)) return set_err(QD_ERR_INVALID_ARGUMENT, "bad gate list");
+    std::vector<qd::SparseGate> gs((size_t)count);
+    std::vector<char> single((size_t)count, 0);
+    for (int32_t i = 0; i < count; ++i) {  // everything is checked before anything is enqueued
+        const qd_gate_desc& d = gates[i];
+        bool cs = false;
+        int rc = sparse_gate_of(s, d.targets, d.k, d.controls, d.values, d.m, d.U, &gs[(size_t)i], &cs);
+        if (rc) return set_err(rc, "gate " + std::to_string(i) + ": " + g_err);
+        single[(size_t)i] = cs;
+    }
+    int rc = sparse_device(s);
+    if (rc) return rc;
+    for (int32_t i = 0; i < count; ++i) {
+        rc = sparse_enqueue(s, gs[(size_t)i], gates[i].U, single[(size_t)i] != 0);
+        if (rc) return set_err(rc, "gate " + std::to_string(i) + ": " + g_err);
+    }
     return QD_OK;
 }
 

@@ -31,6 +31,10 @@ constexpr int kKeyWords = 3;     // a basis index below 2^127 fits three mixed-r
 // multi-kernel path with a radix sort.
 constexpr uint32_t kSparseSmallCap = 1024;
 
+// Matrices of at most this many rows travel inside the kernel arguments of the
+// one-workgroup form (no staging, no read of host memory).
+constexpr int kSparseInlineM = 8;
+
 // A gate as the sparse kernels see it: every target and control as (word,
 // stride inside the word, dim).
 struct SparseGate {
@@ -46,7 +50,8 @@ struct SparseGate {
     uint32_t cv[QD_MAX_CONTROLS];
     int M;                                // class size
     uint64_t off[kSparseMaxM][kKeyWords]; // member a sits at class base + off[a] (word by word)
-    const double2* U;                     // M x M row-major [out][in], device-readable
+    const double2* U;                     // M x M row-major [out][in], device-readable; null: Uin holds it
+    double2 Uin[kSparseInlineM * kSparseInlineM];  // U itself when M <= kSparseInlineM (one-workgroup form)
 };
 
 // Device state of a sparse register. Entries live in one of two slots (the

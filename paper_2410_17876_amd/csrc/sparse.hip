@@ -106,7 +106,7 @@ __global__ __launch_bounds__(kSmallThreads) void sparse_small(const uint64_t* __
             if (ok[w][s] != ok[w][t]) return ok[w][s] < ok[w][t];
         return false;
     };
-    for (uint32_t i = tid; i < (uint32_t)(M * M); i += kSmallThreads) su[i] = g.U[i];
+    for (uint32_t i = tid; i < (uint32_t)(M * M); i += kSmallThreads) su[i] = g.U ? g.U[i] : g.Uin[i];
     for (uint32_t i = tid; i < n; i += kSmallThreads) {
         uint64_t key[kKeyWords] = {0, 0, 0};
         for (int w = 0; w < W; ++w) key[w] = kin[w * cin + i];
@@ -477,6 +477,15 @@ hipError_t sparse_apply(SparseData& d, const SparseGate& g0, const double* U, bo
     if (d.bound == 0) return hipSuccess;  // no entries: nothing to do
     const bool small = d.bound <= kSparseSmallCap / M;
     if (!small && d.bound * M > (uint64_t)INT32_MAX) return hipErrorNotSupported;  // hipCUB counts items in int
+    if (small && M <= (uint64_t)kSparseInlineM) {  // U in the kernel arguments: nothing to stage
+        SparseGate g = g0;
+        g.U = nullptr;
+        std::memcpy(g.Uin, U, M * M * sizeof(double2));
+        QD_TRY(apply_small(d, g));
+        d.bound = cols_single ? d.bound : d.bound * M;
+        d.exact = false;
+        return hipSuccess;
+    }
     // Stage U in the pinned ring (the slot's previous gate has finished once its event has).
     const int slot = (int)(d.uses % SparseData::kURing);
     if (d.uses >= (uint64_t)SparseData::kURing) QD_TRY(hipEventSynchronize(d.uev[slot]));

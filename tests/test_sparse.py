@@ -242,6 +242,26 @@ def test_sparse_gpu_switches_forms_on_the_true_count():
 
 
 @pytest.mark.gpu
+def test_sparse_gpu_gate_list_in_one_call():
+    # qd_sparse_apply_circuit equals gate-by-gate application entry for entry; an
+    # invalid gate anywhere in the list leaves the state unchanged
+    rng = np.random.default_rng(5)
+    dims = [3, 2, 5, 2, 4]  # D = 240: a full state stays small for the oracle, and x 16 passes 1024
+    gates = rand_circuit(rng, dims, 60)
+    a = qd().SparseState(dims).run(gates)
+    b = qd().SparseState(dims)
+    for g in gates:
+        b.apply_gate(g)
+    assert gpu_dict(a) == gpu_dict(b) == soracle.run(dims, gates)
+    before = gpu_dict(a)
+    with pytest.raises(qd().QDError):
+        a.run(gates[:5] + [Gate((0, 0), np.eye(9))] + gates[5:])  # a repeated target
+    assert gpu_dict(a) == before
+    a.close()
+    b.close()
+
+
+@pytest.mark.gpu
 def test_sparse_gpu_errors_leave_state_unchanged():
     rng = np.random.default_rng(3)
     st = qd().SparseState([5, 5, 3])
