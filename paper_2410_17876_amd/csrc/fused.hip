@@ -595,13 +595,13 @@ __device__ __forceinline__ bool chunk_at(const TileGeom& a, const I* __restrict_
     return in && e < a.L;
 }
 
-// Whole tile <-> HBM. Nothing is predicated: a lane past the end of a run or of
-// the tile gets the clamped last element (chunk_at), whose address in HBM and
-// place in the tile belong together, so it loads, writes to LDS and stores back
-// exactly what the lane that owns that element does (the same value to the same
-// address). The compiler issues a wavefront's U4 loads back to back with no wait
-// between them: 256 bytes per lane in flight, a whole 64 KB tile per 256-thread
-// workgroup.
+// Whole tile <-> HBM. A lane past the end of a run or of the tile gets the
+// clamped last element (chunk_at), whose address in HBM and place in the tile
+// belong together, so loads and LDS writes need no predicate: such a lane moves
+// exactly what the lane that owns that element moves (the same value to the
+// same place). The compiler issues a wavefront's U4 loads back to back with no
+// wait between them: 256 bytes per lane in flight, a whole 64 KB tile per
+// 256-thread workgroup.
 template <typename T, typename I, bool LOAD, int BS>
 __device__ __forceinline__ void move_tile(T* __restrict__ psi, T* tile, I obase, const TileGeom& a,
                                           const I* __restrict__ run_off) {
@@ -613,16 +613,20 @@ __device__ __forceinline__ void move_tile(T* __restrict__ psi, T* tile, I obase,
         T v[U4];
         uint32_t t_at[U4];
         I g_off[U4];
+        bool ok[U4];
 #pragma unroll
-        for (int u = 0; u < U4; ++u) (void)chunk_at<I>(a, run_off, k0 + u * nw, lane, &t_at[u], &g_off[u]);
+        for (int u = 0; u < U4; ++u) ok[u] = chunk_at<I>(a, run_off, k0 + u * nw, lane, &t_at[u], &g_off[u]);
         if (LOAD) {
 #pragma unroll
             for (int u = 0; u < U4; ++u) v[u] = ld_stream(psi + obase + g_off[u]);
 #pragma unroll
             for (int u = 0; u < U4; ++u) tile[t_at[u]] = v[u];
         } else {
+            // Stores stay predicated: a duplicate lane's store would be a second,
+            // partial write of the same line (about 1.5% more HBM writes, measured).
 #pragma unroll
-            for (int u = 0; u < U4; ++u) st_stream(psi + obase + g_off[u], tile[t_at[u]]);
+            for (int u = 0; u < U4; ++u)
+                if (ok[u]) st_stream(psi + obase + g_off[u], tile[t_at[u]]);
         }
     }
 }
