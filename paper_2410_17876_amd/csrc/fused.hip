@@ -403,15 +403,21 @@ __device__ __forceinline__ void blk_shift1(typename Cx<R>::T (&x)[UF][SH::J], in
     case k:                                                              \
         if constexpr ((k) < M) {                                         \
             _Pragma("unroll") for (int u = 0; u < UF; ++u) blk_shift<R, SH, P, k>(x[u]); \
+        } else {                                                         \
+            __builtin_unreachable();                                     \
         }                                                                \
         break;
         QD_SHIFT_CASE(1) QD_SHIFT_CASE(2) QD_SHIFT_CASE(3) QD_SHIFT_CASE(4) QD_SHIFT_CASE(5) QD_SHIFT_CASE(6)
 #undef QD_SHIFT_CASE
-        default: break;
+        default: __builtin_unreachable();  // shifts 1 .. d - 1 only
     }
 }
 
-// One gate of a block on UF joint classes.
+// One gate of a block on UF joint classes. The planner emits only codes that fit
+// the block's shape (fusion.cpp checks each one), so every other code is
+// unreachable: with no pass-through path, each case writes its results straight
+// into the registers that carry x to the next gate (a pass-through path makes the
+// compiler copy the whole joint class on every gate).
 template <typename R, class SH, int UF>
 __device__ __forceinline__ void blk_gate(typename Cx<R>::T (&x)[UF][SH::J], const BlockGate* __restrict__ b,
                                          const unsigned char* __restrict__ blob) {
@@ -423,16 +429,24 @@ __device__ __forceinline__ void blk_gate(typename Cx<R>::T (&x)[UF][SH::J], cons
     case kBlkDense1 * 16 + (p)*4:                                                           \
         if constexpr ((p) < SH::L && SH::d(p) <= MM) {                                      \
             _Pragma("unroll") for (int u = 0; u < UF; ++u) blk_dense1<R, SH, p>(x[u], U);   \
+        } else {                                                                            \
+            __builtin_unreachable();                                                        \
         }                                                                                   \
         break;                                                                              \
     case kBlkDiag1 * 16 + (p)*4:                                                            \
         if constexpr ((p) < SH::L) {                                                        \
             const uint32_t om = b->one_mask;                                                \
             _Pragma("unroll") for (int u = 0; u < UF; ++u) blk_diag1<R, SH, p>(x[u], U, om); \
+        } else {                                                                            \
+            __builtin_unreachable();                                                        \
         }                                                                                   \
         break;                                                                              \
     case kBlkShift1 * 16 + (p)*4:                                                           \
-        if constexpr ((p) < SH::L) blk_shift1<R, SH, p, UF>(x, b->shift);                   \
+        if constexpr ((p) < SH::L) {                                                        \
+            blk_shift1<R, SH, p, UF>(x, b->shift);                                          \
+        } else {                                                                            \
+            __builtin_unreachable();                                                        \
+        }                                                                                   \
         break;
         QD_BLK1(0) QD_BLK1(1) QD_BLK1(2)
 #undef QD_BLK1
@@ -440,11 +454,13 @@ __device__ __forceinline__ void blk_gate(typename Cx<R>::T (&x)[UF][SH::J], cons
     case kBlkDense2 * 16 + (p)*4 + (q):                                                        \
         if constexpr ((p) < SH::L && (q) < SH::L && SH::d(p) * SH::d(q) <= MM) {               \
             _Pragma("unroll") for (int u = 0; u < UF; ++u) blk_dense2<R, SH, p, q>(x[u], U);   \
+        } else {                                                                               \
+            __builtin_unreachable();                                                           \
         }                                                                                      \
         break;
         QD_BLK2(0, 1) QD_BLK2(1, 0) QD_BLK2(0, 2) QD_BLK2(2, 0) QD_BLK2(1, 2) QD_BLK2(2, 1)
 #undef QD_BLK2
-        default: break;
+        default: __builtin_unreachable();
     }
 }
 

@@ -58,6 +58,23 @@ int block_kind(const GatePlan& p, int k, int m, int precision, int* shift) {
     return kBlkShift1;
 }
 
+// Whether the device's block switch has a case for this gate code on this block
+// shape (fused.hip treats every other code as unreachable).
+bool block_code_fits(int shape, int code, int shift, int precision) {
+    const int* d = kBlockShapes[shape];
+    const int L = d[1] == 1 ? 1 : (d[2] == 1 ? 2 : 3);
+    if (d[0] * d[1] * d[2] > block_max_j(precision)) return false;
+    const int kind = code / 16, p = (code / 4) % 4, q = code % 4;
+    if (code < 0 || p >= L) return false;
+    switch (kind) {
+        case kBlkDense1: return q == 0 && d[p] <= block_max_m(precision);
+        case kBlkDiag1: return q == 0;
+        case kBlkShift1: return q == 0 && shift >= 1 && shift < d[p];
+        case kBlkDense2: return q < L && q != p && d[p] * d[q] <= block_max_m(precision);
+        default: return false;
+    }
+}
+
 template <typename R>
 void put_complex(unsigned char* dst, double re, double im) {
     R v[2] = {static_cast<R>(re), static_cast<R>(im)};
@@ -251,6 +268,10 @@ int build_fused(const int32_t* dims, int n, int precision, const CircuitGate* ga
                 const int kind = block_kind(gpl, B.k, 0, precision, &sh);
                 auto pos = [&](int q) { return (int)(std::find(T.begin(), T.end(), q) - T.begin()); };
                 bg.code = kind * 16 + pos(B.lt[0]) * 4 + (B.k > 1 ? pos(B.lt[1]) : 0);
+                if (!block_code_fits(shape, bg.code, sh, precision)) {
+                    *err = "internal: register block gate that its shape does not take";
+                    return QD_ERR_NOT_SUPPORTED;
+                }
                 bg.u_off = (uint32_t)udata.size();
                 if (kind == kBlkDense1 || kind == kBlkDense2) {
                     put_u(gates[B.gi].U, gpl.M);

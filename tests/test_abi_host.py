@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 import paper_2410_17876_amd as qd
-from qd_inputs import clock, dft, haar, shift
+from qd_inputs import circuits, clock, dft, haar, shift
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -324,3 +324,28 @@ def test_circuit_plan_bounds_the_device_data_of_a_pass():
     assert len(plan) >= 4                          # the bound, not the targets, closed the passes
     small = qd.circuit_plan(dims, gates, "c64", tile_amps=1024, min_run=64)
     assert len(small) >= len(plan)                 # smaller tiles hold fewer targets per pass
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_planner_emits_only_block_codes_the_device_takes(precision):
+    # Host only: the block kernel treats any gate code its shape cannot take as
+    # unreachable, and the planner refuses to emit one (an internal error). Plan
+    # every block shape's circuits, the 500-gate mixed circuit and random
+    # circuits at several look-ahead windows; none may fail.
+    q = qd
+    max_m = 4 if precision == "c128" else 7
+    rng = np.random.default_rng(77)
+    from test_gpu_fused import BLOCK_SHAPES, block_shape_gates
+    for shape in BLOCK_SHAPES:
+        dims = [2, shape[0], 3, shape[1] if len(shape) > 1 else 2, 2, shape[2] if len(shape) > 2 else 3, 2]
+        gates = block_shape_gates(rng, dims, [1, 3, 5][:len(shape)], 32, max_m)
+        for reorder in (0, 8, 64):
+            q.circuit_plan(dims, gates, precision, tile_amps=1024, min_run=2, reorder=reorder)
+    dims, gates = circuits.large()
+    for reorder in (0, 256):
+        q.circuit_plan(dims, gates, precision, reorder=reorder)
+    for i in range(60):
+        dims = [int(x) for x in rng.integers(2, 8, size=int(rng.integers(3, 9)))]
+        if math.prod(dims) > 2_000_000:
+            continue
+        q.circuit_plan(dims, circuits.random_circuit(dims, 80, i), precision, reorder=int(rng.integers(0, 300)))

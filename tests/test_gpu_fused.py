@@ -198,7 +198,7 @@ def test_plain_circuit_in_one_launch(precision):
     dims, gates = circuits.plain()
     st = qd().State(dims, precision)
     info = st.run_circuit(gates)
-    assert info == {"passes": 1, "fused_passes": 1}
+    assert info["passes"] == info["fused_passes"] == 1
     assert_close(st.amplitudes(), oracle.run(dims, gates), precision, "plain circuit, one launch")
 
 
@@ -349,3 +349,5 @@ def test_register_blocks_every_shape_bitwise(precision):
             assert_close(a.amplitudes(), ref, precision, f"blocks {shape} reorder {reorder}")
             a.close()
             c.close()
+
+
