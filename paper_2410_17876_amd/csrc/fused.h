@@ -68,7 +68,7 @@ constexpr int kChainMaxLen = 16;
 // number of gates and u_off their BlockGate records.
 constexpr int32_t kBlock = 10;      // TileGate::kind of a register block
 constexpr int kBlockMaxJ = 16;
-constexpr int kBlockMaxJ128 = 8;
+constexpr int kBlockMaxJ128 = 12;  // 128 VGPRs in the tile kernels (16 needs 166: fewer waves per SIMD)
 constexpr int kBlockMaxGates = 32;
 
 // Block shapes: the dims of T in joint order (1 pads), joint size at most 16.

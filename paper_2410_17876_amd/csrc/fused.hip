@@ -655,8 +655,10 @@ constexpr int fuse_block() {
     return sizeof(R) == 4 ? 512 : 256;
 }
 
+// Both tile kernels ask for four waves per SIMD (1024 / BS workgroups per CU), the
+// occupancy their LDS allows at the default tiles: at most 128 VGPRs.
 template <typename R, typename I, int BS>
-__global__ __launch_bounds__(BS) void fused_tile(typename Cx<R>::T* __restrict__ psi, const FusedArgs<I> a,
+__global__ __launch_bounds__(BS, 1024 / BS) void fused_tile(typename Cx<R>::T* __restrict__ psi, const FusedArgs<I> a,
                                                          const TileGate* __restrict__ gates,
                                                          const unsigned char* __restrict__ blob,
                                                          const I* __restrict__ run_off) {
@@ -678,7 +680,7 @@ __global__ __launch_bounds__(BS) void fused_tile(typename Cx<R>::T* __restrict__
 // A batched round: workgroup b processes tile (b - first_block) of the item
 // whose block range holds b (binary search over the items' first blocks).
 template <typename R, int BS>
-__global__ __launch_bounds__(BS) void batch_tile(const BatchItem* __restrict__ items, int nitems,
+__global__ __launch_bounds__(BS, 1024 / BS) void batch_tile(const BatchItem* __restrict__ items, int nitems,
                                                          const unsigned char* __restrict__ blob) {
     using T = typename Cx<R>::T;
     extern __shared__ __align__(16) unsigned char smem_raw[];
