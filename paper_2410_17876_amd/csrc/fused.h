@@ -65,7 +65,8 @@ constexpr int kChainMaxLen = 16;
 // runs over T in the block's shape order (dims ascending; ties by tile
 // position), first position least significant; TileGate::off holds the tile
 // offsets of the J joint members, one_mask the shape id (kBlockShapes), M2 the
-// number of gates and u_off their BlockGate records.
+// number of gates, u_off their BlockGate records and dst[0] how many of them have
+// controls outside the tile.
 constexpr int32_t kBlock = 10;      // TileGate::kind of a register block
 constexpr int kBlockMaxJ = 16;
 constexpr int kBlockMaxJ128 = 12;  // 128 VGPRs in the tile kernels (16 needs 166: fewer waves per SIMD)
@@ -79,13 +80,21 @@ constexpr int kBlockShapes[kBlockShapeCount][3] = {
     {2, 2, 2}, {2, 2, 3}, {2, 2, 4}};
 
 // One gate of a block: code = kind * 16 + p * 4 + q, p (and q) the joint
-// positions of its first (and second) target.
+// positions of its first (and second) target. A block gate may have up to
+// kBlockMaxOuter controls on qudits outside the tile: constant over a tile, they
+// decide once per tile whether the gate acts on it (Sec. 2.4), as for a
+// descriptor's outer controls.
 enum BlockKind { kBlkDense1 = 0, kBlkDiag1 = 1, kBlkShift1 = 2, kBlkDense2 = 3 };
+constexpr int kBlockMaxOuter = 2;
 struct BlockGate {
     int32_t code;
     uint32_t u_off;     // blob offset: dense: the M x M matrix; phase: one factor per local index
     uint32_t one_mask;  // phase: bit a set if local index a keeps its amplitude (factor exactly 1)
     int32_t shift;      // shift: |a> -> |a + shift mod d>
+    int32_t n_outer;    // controls outside the tile: the gate acts on a tile iff for every l:
+    uint32_t oc_dim[kBlockMaxOuter];     //   (tile base / oc_stride[l]) mod oc_dim[l] == oc_val[l]
+    uint32_t oc_val[kBlockMaxOuter];
+    uint64_t oc_stride[kBlockMaxOuter];
 };
 
 struct TileGate {

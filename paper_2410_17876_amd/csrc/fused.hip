@@ -464,10 +464,19 @@ __device__ __forceinline__ void blk_gate(typename Cx<R>::T (&x)[UF][SH::J], cons
     }
 }
 
-template <typename R, int D0, int D1, int D2, int BS>
+// Whether a block gate's controls outside the tile hold for the tile at `base`
+// (uniform; I-wide division: 32-bit for registers below 2^31 amplitudes).
+template <typename I>
+__device__ __forceinline__ bool blk_outer_holds(const BlockGate* __restrict__ b, I base) {
+    for (int l = 0; l < b->n_outer; ++l)
+        if ((base / (I)b->oc_stride[l]) % (I)b->oc_dim[l] != (I)b->oc_val[l]) return false;
+    return true;
+}
+
+template <typename R, int D0, int D1, int D2, int BS, typename I>
 __device__ __forceinline__ void tile_block(typename Cx<R>::T* tile, const TileGate* __restrict__ G,
                                            const unsigned char* __restrict__ blob, const uint16_t* bases,
-                                           const uint32_t (&pre)[kPre]) {
+                                           const uint32_t (&pre)[kPre], I obase) {
     using T = typename Cx<R>::T;
     using SH = BlockShape<D0, D1, D2>;
     constexpr int J = SH::J;
@@ -477,6 +486,13 @@ __device__ __forceinline__ void tile_block(typename Cx<R>::T* tile, const TileGa
     for (int a = 0; a < J; ++a) off[a] = G->off[a];
     const BlockGate* __restrict__ bg = reinterpret_cast<const BlockGate*>(blob + G->u_off);
     const int ng = G->M2;
+    // Gates whose outer controls fail on this tile are skipped (bit g clear).
+    uint32_t live = 0xffffffffu;
+    if (G->dst[0] != 0)
+        for (int g = 0; g < ng; ++g) {
+            const BlockGate* __restrict__ b = bg + __builtin_amdgcn_readfirstlane(g);
+            if (b->n_outer > 0 && !blk_outer_holds<I>(b, obase)) live &= ~(1u << g);
+        }
     for_classes<UF, BS>(G, bases, pre, [&](const uint32_t (&base)[UF], const bool (&ok)[UF]) {
         T x[UF][J];
 #pragma unroll
@@ -484,7 +500,8 @@ __device__ __forceinline__ void tile_block(typename Cx<R>::T* tile, const TileGa
 #pragma unroll
             for (int a = 0; a < J; ++a) x[u][a] = tile[base[u] + off[a]];  // clamped bases: unconditional
 #pragma unroll 1
-        for (int g = 0; g < ng; ++g) blk_gate<R, SH, UF>(x, bg + __builtin_amdgcn_readfirstlane(g), blob);
+        for (int g = 0; g < ng; ++g)
+            if ((live >> g) & 1u) blk_gate<R, SH, UF>(x, bg + __builtin_amdgcn_readfirstlane(g), blob);
 #pragma unroll
         for (int u = 0; u < UF; ++u) {
             if (!ok[u]) continue;
@@ -495,10 +512,10 @@ __device__ __forceinline__ void tile_block(typename Cx<R>::T* tile, const TileGa
 }
 
 // A block on its shape (kBlockShapes); complex128 joint classes stop at kBlockMaxJ128.
-template <typename R, int BS>
+template <typename R, int BS, typename I>
 __device__ __forceinline__ void tile_block_shape(typename Cx<R>::T* tile, const TileGate* __restrict__ G,
                                                  const unsigned char* __restrict__ blob, const uint16_t* bases,
-                                                 const uint32_t (&pre)[kPre]) {
+                                                 const uint32_t (&pre)[kPre], I obase) {
     constexpr int JM = sizeof(R) == 8 ? kBlockMaxJ128 : kBlockMaxJ;
     static_assert(kBlockShapeCount == 19, "a case per block shape");
     switch (G->one_mask) {
@@ -506,7 +523,7 @@ __device__ __forceinline__ void tile_block_shape(typename Cx<R>::T* tile, const 
     case id:                                                                                               \
         if constexpr (kBlockShapes[id][0] * kBlockShapes[id][1] * kBlockShapes[id][2] <= JM)               \
             tile_block<R, kBlockShapes[id][0], kBlockShapes[id][1], kBlockShapes[id][2], BS>(tile, G, blob, \
-                                                                                             bases, pre);  \
+                                                                                             bases, pre, obase); \
         break;
         QD_SHAPE(0) QD_SHAPE(1) QD_SHAPE(2) QD_SHAPE(3) QD_SHAPE(4) QD_SHAPE(5) QD_SHAPE(6) QD_SHAPE(7) QD_SHAPE(8)
         QD_SHAPE(9) QD_SHAPE(10) QD_SHAPE(11) QD_SHAPE(12) QD_SHAPE(13) QD_SHAPE(14) QD_SHAPE(15) QD_SHAPE(16)
@@ -540,7 +557,7 @@ __device__ __forceinline__ void apply_gates(typename Cx<R>::T* tile, I obase, in
         const T* U = reinterpret_cast<const T*>(blob + G->u_off);
         const uint16_t* bases = reinterpret_cast<const uint16_t*>(blob + G->bases_off);
         if (G->kind == kBlock) {
-            tile_block_shape<R, BS>(tile, G, blob, bases, pre);
+            tile_block_shape<R, BS>(tile, G, blob, bases, pre, obase);
         } else if (G->kind == kDensePair) {
             switch (G->M * 8 + G->M2) {
 #define QD_PAIR_CASE(m1, m2) \

@@ -198,8 +198,11 @@ int build_fused(const int32_t* dims, int n, int precision, const CircuitGate* ga
     };
     GatePlan joint;  // geometry of a pair's or a block's joint class
     const int jmax = block_max_j(precision);
-    auto in_block = [&](const Local& A) { return block_kind(A.plan, A.k, A.in_tile_controls + A.t.n_outer, precision,
-                                                            nullptr) >= 0; };
+    // Block gates: no controls inside the tile (the joint class then holds whole
+    // classes of the gate) and at most kBlockMaxOuter outside it (a per-tile test).
+    auto in_block = [&](const Local& A) {
+        return A.t.n_outer <= kBlockMaxOuter && block_kind(A.plan, A.k, A.in_tile_controls, precision, nullptr) >= 0;
+    };
     for (size_t i = 0; i < locs.size(); ++i) {
         Local& A = locs[i];
         TileGate t = A.t;
@@ -258,12 +261,20 @@ int build_fused(const int32_t* dims, int n, int precision, const CircuitGate* ga
             t.n_outer = 0;
             for (int a = 0; a < J; ++a) t.off[a] = (uint32_t)joint.off[a];
             t.u_off = (uint32_t)udata.size();
+            t.dst[0] = 0;
             udata.resize(align_up(udata.size() + blen * sizeof(BlockGate), 16));
             for (size_t j = 0; j < blen; ++j) {
                 const Local& B = locs[i + j];
                 const GatePlan& gpl = B.plan;
                 BlockGate bg;
                 std::memset(&bg, 0, sizeof bg);
+                bg.n_outer = B.t.n_outer;
+                for (int l = 0; l < B.t.n_outer; ++l) {
+                    bg.oc_stride[l] = B.t.oc_stride[l];
+                    bg.oc_dim[l] = B.t.oc_dim[l];
+                    bg.oc_val[l] = B.t.oc_val[l];
+                }
+                if (B.t.n_outer > 0) ++t.dst[0];
                 int sh = 0;
                 const int kind = block_kind(gpl, B.k, 0, precision, &sh);
                 auto pos = [&](int q) { return (int)(std::find(T.begin(), T.end(), q) - T.begin()); };
@@ -433,7 +444,8 @@ int plan_circuit(const int32_t* dims, int n, int precision, const CircuitGate* g
     // their fusability, device-data bound and qudit masks.
     struct Info {
         bool skip, can, chain;  // chain: dense with a class small enough for a chain
-        bool block;             // may join a register block
+        bool block;             // may join a register block as it is (no controls)
+        bool blockU;            // would with its controls dropped (it joins one if they all lie outside the tile)
         size_t bytes;
         uint64_t tmask, cmask;
         uint64_t M;
@@ -450,6 +462,7 @@ int plan_circuit(const int32_t* dims, int n, int precision, const CircuitGate* g
             f.can = opt.fuse && fusable(*gp, g.m);
             f.chain = gp->category == kDense && gp->M <= kChainMaxM;
             f.block = block_kind(*gp, g.k, g.m, precision, nullptr) >= 0;
+            f.blockU = g.m <= kBlockMaxOuter && block_kind(*gp, g.k, 0, precision, nullptr) >= 0;
             f.M = (uint64_t)gp->M;
             f.bytes = sizeof(TileGate) + (size_t)tile_bound + (size_t)gp->M * gp->M * 16 + 64;
             f.tmask = f.cmask = 0;
@@ -517,6 +530,22 @@ int plan_circuit(const int32_t* dims, int n, int precision, const CircuitGate* g
             if ((blockA & all) == all) break;
         }
         if (cur.empty()) continue;
+        const bool one_sweep = cur.size() == 1 && !opt.single_as_fused;
+        if (!one_sweep) {
+            // Pad the tile to the budget with the lowest untouched qudits: fewer,
+            // larger workgroups (each has a fixed cost) and longer contiguous runs.
+            for (int q = 0; q < n; ++q)
+                if (!inS[q] && prodS * (uint64_t)dims[q] <= tile_max) {
+                    inS[q] = true;
+                    prodS *= (uint64_t)dims[q];
+                }
+        }
+        uint64_t Smask = 0;
+        for (int q = 0; q < n; ++q)
+            if (inS[q]) Smask |= 1ull << q;
+        // A gate may join a register block if it has no controls, or only
+        // controls outside the tile (build_fused makes the same test).
+        auto blockable = [&](const Info& h) { return h.block || (h.blockU && !(h.cmask & Smask)); };
         if (opt.reorder > 0) {
             // Within the pass, move each chain-sized dense gate back to the last
             // gate on the same classes when it commutes with every gate in
@@ -541,8 +570,8 @@ int plan_circuit(const int32_t* dims, int n, int precision, const CircuitGate* g
             // Then gather register blocks: a block gate takes every later block gate
             // whose targets still fit its joint class (at most 3 qudits and
             // block_max_j amplitudes) and that commutes with every gate it moves
-            // ahead of (block gates have no controls, so: its targets meet none of
-            // their targets or controls).
+            // ahead of: its targets meet none of their targets or controls, and its
+            // controls (outside the tile, if any) meet none of their targets.
             const uint64_t jmax = (uint64_t)block_max_j(precision);
             std::vector<char> used(cur.size(), 0);
             seq.clear();
@@ -551,8 +580,8 @@ int plan_circuit(const int32_t* dims, int n, int precision, const CircuitGate* g
                 used[a] = 1;
                 seq.push_back(cur[a]);
                 const Info& f = info[cur[a]];
-                if (!f.block) continue;
-                uint64_t T = f.tmask, passA = 0;
+                if (!blockable(f)) continue;
+                uint64_t T = f.tmask, passA = 0, passT = 0;
                 for (size_t b = a + 1; b < cur.size(); ++b) {
                     if (used[b]) continue;
                     const Info& h = info[cur[b]];
@@ -564,29 +593,23 @@ int plan_circuit(const int32_t* dims, int n, int precision, const CircuitGate* g
                             J *= (uint64_t)dims[q];
                             ++nq;
                         }
-                    if (h.block && nq <= 3 && J <= jmax && !(h.tmask & passA)) {
+                    if (blockable(h) && nq <= 3 && J <= jmax && !(h.tmask & passA) && !(h.cmask & passT)) {
                         used[b] = 1;
                         seq.push_back(cur[b]);
                         T = U;
                     } else {
                         passA |= h.tmask | h.cmask;
+                        passT |= h.tmask;
                     }
                 }
             }
             cur.swap(seq);
         }
         PassPlan pp;
-        if (cur.size() == 1 && !opt.single_as_fused) {
+        if (one_sweep) {
             pp.fused = false;
             pp.gates = cur;
         } else {
-            // Pad the tile to the budget with the lowest untouched qudits: fewer,
-            // larger workgroups (each has a fixed cost) and longer contiguous runs.
-            for (int q = 0; q < n; ++q)
-                if (!inS[q] && prodS * (uint64_t)dims[q] <= tile_max) {
-                    inS[q] = true;
-                    prodS *= (uint64_t)dims[q];
-                }
             std::vector<int> S;
             for (int q = 0; q < n; ++q)
                 if (inS[q]) S.push_back(q);

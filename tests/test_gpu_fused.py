@@ -351,3 +351,57 @@ def test_register_blocks_every_shape_bitwise(precision):
             c.close()
 
 
+
+
+def outer_control_block_gates(rng, dims, T, C, count, max_m):
+    # 1-qudit gates on the block qudits T, uncontrolled or with one or two
+    # controls on the qudits C (outside small tiles): dense, shifts, phases
+    out = []
+    while len(out) < count:
+        q = int(rng.choice(T))
+        d = dims[q]
+        kind = int(rng.integers(4))
+        if kind == 0 and d <= max_m:
+            U = haar(d, rng)
+        elif kind == 1:
+            U = shift(d, int(rng.integers(1, d)))
+        elif kind == 2:
+            U = np.diag(np.where(rng.random(d) < 0.3, 1.0, np.exp(2j * np.pi * rng.random(d))))
+        else:
+            U = clock(d)
+        nc = int(rng.integers(3))
+        cs = tuple(int(c) for c in rng.choice(C, nc, replace=False))
+        out.append(Gate((q,), U, cs, tuple(int(rng.integers(dims[c])) for c in cs)))
+    return out
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_register_blocks_with_outer_controls_bitwise(precision):
+    # Gates whose controls all lie outside the tile join register blocks; each
+    # tile applies only the gates whose outer controls hold on it. Fused equals
+    # one sweep per gate bit for bit (given order and planned order) and the
+    # oracle within the tolerances.
+    q = qd()
+    dims = [2] * 5 + [2, 3, 2] + [3, 2, 3, 2]
+    T, C = [5, 6, 7], [8, 9, 10, 11]
+    max_m = 4 if precision == "c128" else 7
+    rng = np.random.default_rng(515)
+    gates = outer_control_block_gates(rng, dims, T, C, 60, max_m)
+    gates.insert(30, Gate((5, 7), haar(4, rng)))          # an uncontrolled two-qudit gate in the block's qudits
+    gates.insert(45, Gate((0,), shift(2), (9,), (1,)))    # a gate outside the block's qudits
+    psi0 = rand_state(rng, math.prod(dims))
+    for reorder in (0, 64):
+        passes, order = q.circuit_plan(dims, gates, precision, tile_amps=256, min_run=32, reorder=reorder,
+                                       with_order=True)
+        a = q.State(dims, precision, init=None).set_amplitudes(psi0)
+        a.run_circuit(gates, tile_amps=256, min_run=32, reorder=reorder)
+        c = q.State(dims, precision, init=None).set_amplitudes(psi0)
+        c.run([gates[i] for i in order])
+        assert np.array_equal(a.amplitudes(), c.amplitudes()), f"reorder {reorder}"
+        ref = psi0.copy() if precision == "c128" else (psi0.real.astype(np.float32).astype(np.float64) +
+                                                       1j * psi0.imag.astype(np.float32).astype(np.float64))
+        for g in gates:
+            oracle.apply_gate(dims, ref, g)
+        assert_close(a.amplitudes(), ref, precision, f"outer-controlled blocks, reorder {reorder}")
+        a.close()
+        c.close()
