@@ -54,7 +54,8 @@ constexpr int32_t kDenseChain = 9;  // TileGate::kind of a chain; M2 = its lengt
 constexpr int kChainMaxM = 3;  // at 4, one gate's matrix (64 scalar registers in complex128) spills
 constexpr int kChainMaxLen = 16;
 
-// A register block: a run of uncontrolled gates whose targets all lie in a set T
+// A register block: a run of gates with no controls inside the tile (controls
+// outside it are constant per tile: see BlockGate) whose targets all lie in a set T
 // of at most 3 tile qudits with at most kBlockMaxJ (complex64) or
 // kBlockMaxJ128 (complex128) amplitudes in the joint class over T. A thread reads
 // a joint class (the amplitudes that differ only in the T digits) from LDS
