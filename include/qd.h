@@ -25,7 +25,12 @@
  *     abort crosses the ABI. qd_last_error() returns a thread-local message for
  *     the last failing call of the calling thread.
  *   - Arguments are validated on the host before any device work, so invalid
- *     input never reaches a kernel.
+ *     input never reaches a kernel. Unitarity of U is the caller's contract; with
+ *     the environment variable QD_CHECK_UNITARY set to anything but "0", every
+ *     gate given to the library is also checked: each entry of U^dagger U - I
+ *     must be at most 1e-10 in modulus (finite entries only), else the call fails
+ *     with QD_ERR_INVALID_ARGUMENT before any work (a debugging aid: it costs
+ *     O(M^3) host flops per gate).
  *   - The caller owns every array it passes; the library copies what it keeps
  *     before returning, so inputs may be freed or reused right away.
  *   - Calls that enqueue device work (apply, reset) are asynchronous on the

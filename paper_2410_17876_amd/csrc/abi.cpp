@@ -567,6 +567,8 @@ int sparse_gate_of(const qd_sparse* s, const int32_t* targets, int32_t k, const 
         g.M *= s->dims[targets[l]];
     }
     if (g.M > qd::kSparseMaxM) return set_err(QD_ERR_NOT_SUPPORTED, "sparse gates act on at most 16 amplitudes");
+    if (unitary_check_enabled() && !(unitary_deviation(U, g.M) <= kUnitaryTol))
+        return set_err(QD_ERR_INVALID_ARGUMENT, "U is not unitary (QD_CHECK_UNITARY)");
     g.m = m;
     for (int l = 0; l < m; ++l) {
         g.cw[l] = s->word[controls[l]];

@@ -10,7 +10,9 @@
 // monomial U that map |a> to itself with factor exactly 1 are identity columns
 // and are skipped, so e.g. a qudit Z gate does not touch the amplitudes with
 // target digit 0.
+#include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "planner.h"
@@ -146,6 +148,31 @@ int check_gate(const int32_t* dims, int32_t n, const int32_t* targets, int32_t k
 
 static bool is_zero(const double* U, int i) { return U[2 * i] == 0.0 && U[2 * i + 1] == 0.0; }
 
+bool unitary_check_enabled() {
+    const char* e = getenv("QD_CHECK_UNITARY");
+    return e && e[0] && !(e[0] == '0' && e[1] == 0);
+}
+
+// max over (r, c) of |(U^dagger U)_rc - [r == c]| for an M x M row-major
+// interleaved complex U (NaN if an entry is not finite).
+double unitary_deviation(const double* U, int M) {
+    double worst = 0.0;
+    for (int r = 0; r < M; ++r)
+        for (int c = 0; c < M; ++c) {
+            double re = 0.0, im = 0.0;  // sum_a conj(U[a][r]) U[a][c]
+            for (int a = 0; a < M; ++a) {
+                const double ur = U[2 * ((size_t)a * M + r)], ui = U[2 * ((size_t)a * M + r) + 1];
+                const double vr = U[2 * ((size_t)a * M + c)], vi = U[2 * ((size_t)a * M + c) + 1];
+                re += ur * vr + ui * vi;
+                im += ur * vi - ui * vr;
+            }
+            const double d = std::hypot(re - (r == c ? 1.0 : 0.0), im);
+            if (std::isnan(d)) return d;
+            if (d > worst) worst = d;
+        }
+    return worst;
+}
+
 int plan_gate(const int32_t* dims, int32_t n, const int32_t* targets, int32_t k, const int32_t* controls,
               const int32_t* values, int32_t m, const double* U, GatePlan* p, std::string* err) {
     int rc = check_gate(dims, n, targets, k, controls, values, m, err);
@@ -185,6 +212,11 @@ int plan_gate(const int32_t* dims, int32_t n, const int32_t* targets, int32_t k,
         p->off[a] = off;
     }
     if (!U) return fail(err, QD_ERR_INVALID_ARGUMENT, "U is null");
+    if (unitary_check_enabled()) {
+        const double dev = unitary_deviation(U, M);
+        if (!(dev <= kUnitaryTol))
+            return fail(err, QD_ERR_INVALID_ARGUMENT, "U is not unitary: max |(U^dagger U - I)_rc| = %.3g", dev);
+    }
 
     // Category from the exact zero pattern.
     bool diag = true;

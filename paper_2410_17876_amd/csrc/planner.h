@@ -33,6 +33,10 @@ int check_gate_shape(const int32_t* dims, int32_t n, const int32_t* targets, int
 constexpr int kSparseKeyWords = 3;
 int sparse_layout(const int32_t* dims, int32_t n, int* word, uint64_t* stride, int* W, uint64_t* P, uint64_t* D_lo,
                   uint64_t* D_hi, std::string* err);
+// Optional unitarity check of gate matrices (QD_CHECK_UNITARY in the environment).
+constexpr double kUnitaryTol = 1e-10;
+bool unitary_check_enabled();
+double unitary_deviation(const double* U, int M);
 int plan_gate(const int32_t* dims, int32_t n, const int32_t* targets, int32_t k, const int32_t* controls,
               const int32_t* values, int32_t m, const double* U, GatePlan* p, std::string* err);
 void plan_info(const GatePlan& p, int precision, qd_gate_info* info);

@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 import paper_2410_17876_amd as qd
-from qd_inputs import circuits, clock, dft, haar, shift
+from qd_inputs import Gate, circuits, clock, dft, haar, shift
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -349,3 +349,32 @@ def test_planner_emits_only_block_codes_the_device_takes(precision):
         if math.prod(dims) > 2_000_000:
             continue
         q.circuit_plan(dims, circuits.random_circuit(dims, 80, i), precision, reorder=int(rng.integers(0, 300)))
+
+
+def test_unitarity_check_on_request(monkeypatch):
+    # Unitarity is the caller's contract; QD_CHECK_UNITARY makes the library check
+    # every gate (each entry of U^dagger U - I at most 1e-10) before any work.
+    rng = np.random.default_rng(12)
+    dims = [2, 3, 5]
+    U = haar(15, rng)
+    bad = U.copy()
+    bad[3, 4] += 1e-6                        # no longer unitary
+    nan = U.copy()
+    nan[0, 0] = np.nan
+    near = U * (1 + 1e-12)                   # unitary within the tolerance
+    monkeypatch.delenv("QD_CHECK_UNITARY", raising=False)
+    qd.gate_info(dims, (1, 2), bad)          # unchecked by default
+    for value in ("1", "yes"):
+        monkeypatch.setenv("QD_CHECK_UNITARY", value)
+        qd.gate_info(dims, (1, 2), U)
+        qd.gate_info(dims, (1, 2), near)
+        for M in (bad, nan):
+            with pytest.raises(qd.QDError) as e:
+                qd.gate_info(dims, (1, 2), M)
+            assert e.value.code == -1 and "unitary" in str(e.value)
+        with pytest.raises(qd.QDError):      # gate lists are checked gate by gate
+            qd.circuit_plan(dims, [Gate((0,), haar(2, rng)), Gate((1, 2), bad)], "c128")
+        with pytest.raises(qd.QDError):      # controlled gates as well
+            qd.gate_info(dims, (0,), np.array([[1, 0], [0, 2.0]]), (1,), (2,))
+    monkeypatch.setenv("QD_CHECK_UNITARY", "0")
+    qd.gate_info(dims, (1, 2), bad)

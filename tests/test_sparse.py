@@ -262,11 +262,15 @@ def test_sparse_gpu_gate_list_in_one_call():
 
 
 @pytest.mark.gpu
-def test_sparse_gpu_errors_leave_state_unchanged():
+def test_sparse_gpu_errors_leave_state_unchanged(monkeypatch):
     rng = np.random.default_rng(3)
     st = qd().SparseState([5, 5, 3])
     st.apply((0,), dft(5))
     before = gpu_dict(st)
+    monkeypatch.setenv("QD_CHECK_UNITARY", "1")  # a non-unitary gate is refused when checking is on
+    with pytest.raises(qd().QDError):
+        st.apply((1,), 2.0 * dft(5))
+    monkeypatch.delenv("QD_CHECK_UNITARY")
     with pytest.raises(qd().QDError):
         st.apply((0, 1), haar(25, rng))  # 25 > 16 amplitudes per class
     with pytest.raises(qd().QDError):
