@@ -66,8 +66,8 @@ constexpr int kChainMaxLen = 16;
 // runs over T in the block's shape order (dims ascending; ties by tile
 // position), first position least significant; TileGate::off holds the tile
 // offsets of the J joint members, one_mask the shape id (kBlockShapes), M2 the
-// number of gates, u_off their BlockGate records and dst[0] how many of them have
-// controls outside the tile.
+// number of gates, u_off their BlockGate records (then their BlockOuter records)
+// and dst[0] how many of them have controls outside the tile.
 constexpr int32_t kBlock = 10;      // TileGate::kind of a register block
 constexpr int kBlockMaxJ = 16;
 constexpr int kBlockMaxJ128 = 12;  // 128 VGPRs in the tile kernels (16 needs 166: fewer waves per SIMD)
@@ -81,20 +81,29 @@ constexpr int kBlockShapes[kBlockShapeCount][3] = {
     {2, 2, 2}, {2, 2, 3}, {2, 2, 4}};
 
 // One gate of a block: code = kind * 16 + p * 4 + q, p (and q) the joint
-// positions of its first (and second) target. A block gate may have up to
-// kBlockMaxOuter controls on qudits outside the tile: constant over a tile, they
-// decide once per tile whether the gate acts on it (Sec. 2.4), as for a
-// descriptor's outer controls.
+// positions of its first (and second) target.
 enum BlockKind { kBlkDense1 = 0, kBlkDiag1 = 1, kBlkShift1 = 2, kBlkDense2 = 3 };
-constexpr int kBlockMaxOuter = 2;
 struct BlockGate {
     int32_t code;
     uint32_t u_off;     // blob offset: dense: the M x M matrix; phase: one factor per local index
     uint32_t one_mask;  // phase: bit a set if local index a keeps its amplitude (factor exactly 1)
     int32_t shift;      // shift: |a> -> |a + shift mod d>
-    int32_t n_outer;    // controls outside the tile: the gate acts on a tile iff for every l:
-    uint32_t oc_dim[kBlockMaxOuter];     //   (tile base / oc_stride[l]) mod oc_dim[l] == oc_val[l]
+};
+
+// A block gate may have up to kBlockMaxOuter controls on qudits outside the tile:
+// constant over a tile, they decide once per tile whether the gate acts on it
+// (Sec. 2.4), as for a descriptor's outer controls. Such a gate has a BlockOuter
+// record; a block's records follow its BlockGate array (TileGate::dst[0] of
+// them, at most kBlockMaxOuterGates).
+constexpr int kBlockMaxOuter = 2;
+constexpr int kBlockMaxOuterGates = kBlockMaxGates;
+struct BlockOuter {
+    uint32_t gate;      // index of the gate in the block
+    int32_t n_outer;    // the gate acts on a tile iff for every l < n_outer:
+    uint32_t oc_dim[kBlockMaxOuter];   //   (tile base / oc_stride[l]) mod oc_dim[l] == oc_val[l]
     uint32_t oc_val[kBlockMaxOuter];
+    FastDiv<uint32_t> oc_sdiv[kBlockMaxOuter];  // the same divisions for 32-bit tile bases
+    FastDiv<uint32_t> oc_ddiv[kBlockMaxOuter];
     uint64_t oc_stride[kBlockMaxOuter];
 };
 

@@ -465,11 +465,19 @@ __device__ __forceinline__ void blk_gate(typename Cx<R>::T (&x)[UF][SH::J], cons
 }
 
 // Whether a block gate's controls outside the tile hold for the tile at `base`
-// (uniform; I-wide division: 32-bit for registers below 2^31 amplitudes).
+// (uniform): multiply-high divisions for 32-bit bases, plain ones for 64-bit.
 template <typename I>
-__device__ __forceinline__ bool blk_outer_holds(const BlockGate* __restrict__ b, I base) {
-    for (int l = 0; l < b->n_outer; ++l)
-        if ((base / (I)b->oc_stride[l]) % (I)b->oc_dim[l] != (I)b->oc_val[l]) return false;
+__device__ __forceinline__ bool blk_outer_holds(const BlockOuter* __restrict__ o, I base) {
+    for (int l = 0; l < o->n_outer; ++l) {
+        I digit;
+        if constexpr (sizeof(I) == 4) {
+            const uint32_t q = fast_div<uint32_t>(base, o->oc_sdiv[l]);
+            digit = q - fast_div<uint32_t>(q, o->oc_ddiv[l]) * o->oc_dim[l];
+        } else {
+            digit = (base / (I)o->oc_stride[l]) % (I)o->oc_dim[l];
+        }
+        if (digit != (I)o->oc_val[l]) return false;
+    }
     return true;
 }
 
@@ -488,11 +496,11 @@ __device__ __forceinline__ void tile_block(typename Cx<R>::T* tile, const TileGa
     const int ng = G->M2;
     // Gates whose outer controls fail on this tile are skipped (bit g clear).
     uint32_t live = 0xffffffffu;
-    if (G->dst[0] != 0)
-        for (int g = 0; g < ng; ++g) {
-            const BlockGate* __restrict__ b = bg + __builtin_amdgcn_readfirstlane(g);
-            if (b->n_outer > 0 && !blk_outer_holds<I>(b, obase)) live &= ~(1u << g);
-        }
+    const BlockOuter* __restrict__ bo = reinterpret_cast<const BlockOuter*>(bg + ng);
+    for (uint32_t i = 0; i < G->dst[0]; ++i) {
+        const BlockOuter* __restrict__ o = bo + __builtin_amdgcn_readfirstlane(i);
+        if (!blk_outer_holds<I>(o, obase)) live &= ~(1u << o->gate);
+    }
     for_classes<UF, BS>(G, bases, pre, [&](const uint32_t (&base)[UF], const bool (&ok)[UF]) {
         T x[UF][J];
 #pragma unroll

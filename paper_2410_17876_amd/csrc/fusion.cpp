@@ -212,8 +212,10 @@ int build_fused(const int32_t* dims, int n, int precision, const CircuitGate* ga
         std::vector<int> T;  // tile-local qudits of the block
         if (in_block(A)) {
             uint64_t J = 1;
+            int nouter = 0;
             while (i + blen < locs.size() && blen < (size_t)kBlockMaxGates && in_block(locs[i + blen])) {
                 const Local& B = locs[i + blen];
+                if (B.t.n_outer > 0 && nouter == kBlockMaxOuterGates) break;
                 std::vector<int> U = T;
                 uint64_t JU = J;
                 for (int l = 0; l < B.k; ++l)
@@ -225,6 +227,7 @@ int build_fused(const int32_t* dims, int n, int precision, const CircuitGate* ga
                 T.swap(U);
                 J = JU;
                 ++blen;
+                if (B.t.n_outer > 0) ++nouter;
             }
         }
         if (blen >= 2) {
@@ -262,19 +265,31 @@ int build_fused(const int32_t* dims, int n, int precision, const CircuitGate* ga
             for (int a = 0; a < J; ++a) t.off[a] = (uint32_t)joint.off[a];
             t.u_off = (uint32_t)udata.size();
             t.dst[0] = 0;
-            udata.resize(align_up(udata.size() + blen * sizeof(BlockGate), 16));
+            for (size_t j = 0; j < blen; ++j) t.dst[0] += locs[i + j].t.n_outer > 0 ? 1u : 0u;
+            const size_t outer_at = t.u_off + blen * sizeof(BlockGate);
+            udata.resize(align_up(outer_at + t.dst[0] * sizeof(BlockOuter), 16));
+            uint32_t no = 0;
             for (size_t j = 0; j < blen; ++j) {
                 const Local& B = locs[i + j];
                 const GatePlan& gpl = B.plan;
+                if (B.t.n_outer > 0) {
+                    BlockOuter bo;
+                    std::memset(&bo, 0, sizeof bo);
+                    bo.gate = (uint32_t)j;
+                    bo.n_outer = B.t.n_outer;
+                    for (int l = 0; l < B.t.n_outer; ++l) {
+                        bo.oc_stride[l] = B.t.oc_stride[l];
+                        bo.oc_dim[l] = B.t.oc_dim[l];
+                        bo.oc_val[l] = B.t.oc_val[l];
+                        if (D < (1ull << 31)) {
+                            bo.oc_sdiv[l] = make_fast_div<uint32_t>(B.t.oc_stride[l]);
+                            bo.oc_ddiv[l] = make_fast_div<uint32_t>(B.t.oc_dim[l]);
+                        }
+                    }
+                    std::memcpy(udata.data() + outer_at + (no++) * sizeof(BlockOuter), &bo, sizeof bo);
+                }
                 BlockGate bg;
                 std::memset(&bg, 0, sizeof bg);
-                bg.n_outer = B.t.n_outer;
-                for (int l = 0; l < B.t.n_outer; ++l) {
-                    bg.oc_stride[l] = B.t.oc_stride[l];
-                    bg.oc_dim[l] = B.t.oc_dim[l];
-                    bg.oc_val[l] = B.t.oc_val[l];
-                }
-                if (B.t.n_outer > 0) ++t.dst[0];
                 int sh = 0;
                 const int kind = block_kind(gpl, B.k, 0, precision, &sh);
                 auto pos = [&](int q) { return (int)(std::find(T.begin(), T.end(), q) - T.begin()); };
