@@ -108,20 +108,22 @@ struct BlockOuter {
 };
 
 struct TileGate {
+    // Fields every gate reads come first (the kernel reads them through the
+    // scalar cache: fewer cache lines per descriptor).
     int32_t kind;        // kDense, kDensePair, kDenseChain, kBlock, or kMonomial for monomial and diagonal gates
     int32_t M;           // dense, chain: class size; pair: class size of the first gate; monomial: active entries
     int32_t M2;          // pair: class size of the second gate (its U follows the first's in the blob);
                          // chain: number of gates
     uint32_t n_classes;                 // classes of the gate inside one tile
     uint32_t bases_off;                 // byte offset of the uint16 class bases in the blob
-    uint32_t off[kFuseMaxM];            // dense, pair, chain: member offsets; monomial: source offsets
-    uint32_t dst[kFuseMaxM];            // monomial: destination offsets
+    uint32_t u_off;                     // byte offset of U (dense) or the factors (monomial) in the blob
     uint32_t one_mask;                  // monomial: bit i set if factor i is exactly 1
     int32_t n_outer;                    // controls outside S
+    uint32_t off[kFuseMaxM];            // dense, pair, chain: member offsets; monomial: source offsets
+    uint32_t dst[kFuseMaxM];            // monomial: destination offsets
     uint64_t oc_stride[kMaxOuterCtl];   // the gate runs on a tile iff for every l:
     uint32_t oc_dim[kMaxOuterCtl];      //   (tile base / oc_stride[l]) mod oc_dim[l] == oc_val[l]
     uint32_t oc_val[kMaxOuterCtl];
-    uint32_t u_off;                     // byte offset of U (dense) or the factors (monomial) in the blob
 };
 
 // Scalar kernel arguments of a fused pass. The device arrays (gate descriptors,
