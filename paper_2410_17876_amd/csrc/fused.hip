@@ -5,11 +5,13 @@
 // the tile back. fused_tile serves a single state, batch_tile one tile of one
 // (state, pass) item of a batched round.
 //
-// Several workgroups share a CU (two 64 KB complex64 tiles; three 48 KB
-// complex128 tiles at the default 3072 amplitudes), so one's loads and stores
-// overlap the others' LDS work. A persistent variant with one 512-thread workgroup per CU
-// that prefetched the next tile into registers measured slower (the LDS phase
-// then has no other workgroup to hide its latency) and was dropped.
+// Several workgroups share a CU (two 64 KB complex64 tiles; three or four
+// complex128 tiles of 36-48 KB), so one's loads and stores overlap the others'
+// LDS work. Persistent variants measured slower and were dropped: one 512-thread
+// workgroup per CU prefetching the next tile into registers (the LDS phase then
+// has no other workgroup to hide its latency), and double-buffered workgroups
+// loading the next tile straight into LDS (one or two tiles in flight per CU
+// cannot keep HBM busy; the plain form's load phases have four).
 #include <hip/hip_runtime.h>
 
 #include "device.h"
