@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <mutex>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -630,10 +631,16 @@ int qd_sparse_apply_circuit(qd_sparse* s, const qd_gate_desc* gates, int32_t cou
     }
     int rc = sparse_device(s);
     if (rc) return rc;
+    std::vector<const double*> us((size_t)count);
+    std::unique_ptr<bool[]> cs(new bool[(size_t)count + 1]);
     for (int32_t i = 0; i < count; ++i) {
-        rc = sparse_enqueue(s, gs[(size_t)i], gates[i].U, single[(size_t)i] != 0);
-        if (rc) return set_err(rc, "gate " + std::to_string(i) + ": " + g_err);
+        us[(size_t)i] = gates[i].U;
+        cs[(size_t)i] = single[(size_t)i] != 0;
     }
+    hipError_t e = qd::sparse_apply_list(s->d, gs.data(), us.data(), cs.get(), count);
+    if (e == hipErrorNotSupported)
+        return set_err(QD_ERR_NOT_SUPPORTED, "sparse state too large: stored entries x class size must stay below 2^31");
+    if (e != hipSuccess) return sparse_hip_err(e, "sparse gate list");
     return QD_OK;
 }
 

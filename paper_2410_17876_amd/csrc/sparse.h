@@ -78,6 +78,15 @@ struct SparseData {
     double2* udev = nullptr;      // the same memory as the device addresses it
     hipEvent_t uev[kURing] = {};
     uint64_t uses = 0;
+    // Runs of one-workgroup gates applied by one launch (sparse_apply_list):
+    // their SparseGate records are staged in pinned host memory and copied to a
+    // device buffer; the staging is reused once the event after its copy has passed.
+    SparseGate* rhost = nullptr;
+    size_t rhost_gates = 0;
+    void* rdev = nullptr;
+    size_t rdev_bytes = 0;
+    hipEvent_t rev = nullptr;
+    bool rev_pending = false;
 };
 
 // Entry pointers of a slot with capacity cap: W key arrays, then amplitudes.
@@ -98,6 +107,14 @@ void sparse_release(SparseData& d);
 // U has at most one nonzero, so the gate cannot raise the entry count. On an
 // error nothing is changed.
 hipError_t sparse_apply(SparseData& d, const SparseGate& g, const double* U, bool cols_single);
+
+// Enqueue a gate list in order, as sparse_apply gate by gate (the same bits).
+// While the host's bound keeps consecutive gates within the one-workgroup form
+// (and their matrices fit the kernel arguments), such a run of gates is applied
+// by one launch that keeps the entries in LDS from gate to gate. On an error the
+// gates before the failing one may have been applied.
+hipError_t sparse_apply_list(SparseData& d, const SparseGate* gates, const double* const* U, const bool* cols_single,
+                             int count);
 
 // Wait for the stream and return the entry count.
 hipError_t sparse_count(SparseData& d, uint64_t* nnz);

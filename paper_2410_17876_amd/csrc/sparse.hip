@@ -27,6 +27,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <vector>
 
 #include "sparse.h"
 
@@ -35,6 +36,9 @@ namespace qd {
 namespace {
 
 constexpr int kSmallThreads = 512;
+constexpr int kRunChunk = 24;  // gate records a run keeps in LDS at a time
+typedef unsigned long long U64x2 __attribute__((ext_vector_type(2)));
+static_assert(sizeof(SparseGate) % 16 == 0, "gate records are copied in 16-byte pieces");
 constexpr uint32_t kSmallIn = kSparseSmallCap / 2;  // entries of a small gate (class size >= 2)
 constexpr int kErrWord = 2;                         // nnz_dev[2]: set if a small gate saw more entries than planned
 
@@ -72,49 +76,49 @@ __device__ __forceinline__ double2 class_row(const double2* U, const double2 (&x
     return double2{yr, yi};
 }
 
-// The whole gate in one workgroup. Input: n = nin[0] entries (key words
-// kin[w * cin + i], amplitudes ain[i]); output: the sorted kept results at kout /
-// aout (capacity cout) and their count at nout[0]. Entry i's results go to
-// output slots i * M .. i * M + M - 1 (only a group's first entry fills them).
-__global__ __launch_bounds__(kSmallThreads) void sparse_small(const uint64_t* __restrict__ kin,
-                                                              const double2* __restrict__ ain, uint64_t cin,
-                                                              uint64_t* __restrict__ counts, int src, int dst,
-                                                              uint64_t* __restrict__ kout, double2* __restrict__ aout,
-                                                              uint64_t cout, const SparseGate g) {
-    __shared__ uint64_t gk[kKeyWords][kSmallIn];
-    __shared__ int32_t la[kSmallIn];
-    __shared__ uint64_t ok[kKeyWords][kSparseSmallCap];
-    __shared__ double2 oa[kSparseSmallCap];
-    __shared__ uint8_t of[kSparseSmallCap];
-    __shared__ double2 su[kSparseMaxM * kSparseMaxM];
-    __shared__ uint32_t kept;
+// LDS of the one-workgroup form: the gate's grouping and its results.
+struct SmallLds {
+    uint64_t gk[kKeyWords][kSmallIn];  // group keys (class bases, or the key itself)
+    int32_t la[kSmallIn];              // local indices (-1: controls fail)
+    uint64_t ok[kKeyWords][kSparseSmallCap];
+    double2 oa[kSparseSmallCap];
+    uint8_t of[kSparseSmallCap];       // output slot holds a kept result
+    double2 su[kSparseMaxM * kSparseMaxM];
+    uint32_t kept;
+};
+
+// One gate on n <= kSmallIn entries (n * M <= kSparseSmallCap), the whole
+// workgroup: key word w of entry i is kin(w, i), its amplitude ain(i); the kept
+// results are handed, in key order, to put(rank, s) (output slot s of L). Entry
+// i's results take output slots i * M .. i * M + M - 1 (only a group's first
+// entry fills them). Returns the kept count (after a barrier; uniform). The
+// inputs are last read before the second barrier and put runs after it, so put
+// may overwrite them.
+template <typename KIn, typename AIn, typename Put>
+__device__ __forceinline__ uint32_t small_gate(const SparseGate& g, const double2* U, uint32_t n, SmallLds& L,
+                                               const KIn& kin, const AIn& ain, const Put& put) {
     const uint32_t tid = threadIdx.x;
     const int W = g.W, M = g.M;
-    const uint64_t n64 = counts[src];
-    if (n64 > kSmallIn || n64 * (uint64_t)M > kSparseSmallCap) {  // the host's bound was wrong: report, change nothing
-        if (tid == 0) counts[kErrWord] = 1;
-        return;
-    }
-    const uint32_t n = (uint32_t)n64, T = n * (uint32_t)M;
+    const uint32_t T = n * (uint32_t)M;
     auto same = [&](uint32_t i, uint32_t j) {
         for (int w = 0; w < W; ++w)
-            if (gk[w][i] != gk[w][j]) return false;
+            if (L.gk[w][i] != L.gk[w][j]) return false;
         return true;
     };
     auto less = [&](uint32_t s, uint32_t t) {  // key of output s < key of output t
         for (int w = W - 1; w >= 0; --w)
-            if (ok[w][s] != ok[w][t]) return ok[w][s] < ok[w][t];
+            if (L.ok[w][s] != L.ok[w][t]) return L.ok[w][s] < L.ok[w][t];
         return false;
     };
-    for (uint32_t i = tid; i < (uint32_t)(M * M); i += kSmallThreads) su[i] = g.U ? g.U[i] : g.Uin[i];
+    for (uint32_t i = tid; i < (uint32_t)(M * M); i += kSmallThreads) L.su[i] = U[i];
     for (uint32_t i = tid; i < n; i += kSmallThreads) {
         uint64_t key[kKeyWords] = {0, 0, 0};
-        for (int w = 0; w < W; ++w) key[w] = kin[w * cin + i];
-        la[i] = classify(g, key);
-        for (int w = 0; w < kKeyWords; ++w) gk[w][i] = key[w];
+        for (int w = 0; w < W; ++w) key[w] = kin(w, i);
+        L.la[i] = classify(g, key);
+        for (int w = 0; w < kKeyWords; ++w) L.gk[w][i] = key[w];
     }
-    for (uint32_t s = tid; s < T; s += kSmallThreads) of[s] = 0;
-    if (tid == 0) kept = 0;
+    for (uint32_t s = tid; s < T; s += kSmallThreads) L.of[s] = 0;
+    if (tid == 0) L.kept = 0;
     __syncthreads();
     for (uint32_t i = tid; i < n; i += kSmallThreads) {
         bool lead = true;
@@ -125,10 +129,10 @@ __global__ __launch_bounds__(kSmallThreads) void sparse_small(const uint64_t* __
             }
         if (!lead) continue;
         const uint32_t o = i * (uint32_t)M;
-        if (la[i] < 0) {  // controls fail: unchanged
-            for (int w = 0; w < kKeyWords; ++w) ok[w][o] = gk[w][i];
-            oa[o] = ain[i];
-            of[o] = 1;
+        if (L.la[i] < 0) {  // controls fail: unchanged
+            for (int w = 0; w < kKeyWords; ++w) L.ok[w][o] = L.gk[w][i];
+            L.oa[o] = ain(i);
+            L.of[o] = 1;
             continue;
         }
         double2 x[kSparseMaxM];
@@ -136,31 +140,114 @@ __global__ __launch_bounds__(kSmallThreads) void sparse_small(const uint64_t* __
         uint32_t present = 0;
         for (uint32_t j = i; j < n; ++j)
             if (same(i, j)) {
-                x[la[j]] = ain[j];
-                present |= 1u << la[j];
+                x[L.la[j]] = ain(j);
+                present |= 1u << L.la[j];
             }
         for (int r = 0; r < M; ++r) {
-            const double2 y = class_row(su, x, present, r, M);
-            for (int w = 0; w < kKeyWords; ++w) ok[w][o + r] = gk[w][i] + g.off[r][w];
-            oa[o + r] = y;
-            of[o + r] = (y.x != 0.0 || y.y != 0.0) ? 1 : 0;
+            const double2 y = class_row(L.su, x, present, r, M);
+            for (int w = 0; w < kKeyWords; ++w) L.ok[w][o + r] = L.gk[w][i] + g.off[r][w];
+            L.oa[o + r] = y;
+            L.of[o + r] = (y.x != 0.0 || y.y != 0.0) ? 1 : 0;
         }
     }
     __syncthreads();
     uint32_t mine = 0;
-    for (uint32_t s = tid; s < T; s += kSmallThreads) mine += of[s];
-    if (mine) atomicAdd(&kept, mine);
+    for (uint32_t s = tid; s < T; s += kSmallThreads) mine += L.of[s];
+    if (mine) atomicAdd(&L.kept, mine);
     // Each kept result goes to its rank among the kept keys (keys are distinct:
     // classes are disjoint and control-failing keys meet no class).
     for (uint32_t s = tid; s < T; s += kSmallThreads) {
-        if (!of[s]) continue;
+        if (!L.of[s]) continue;
         uint32_t rank = 0;
-        for (uint32_t t = 0; t < T; ++t) rank += (of[t] && less(t, s)) ? 1u : 0u;
-        for (int w = 0; w < W; ++w) kout[w * cout + rank] = ok[w][s];
-        aout[rank] = oa[s];
+        for (uint32_t t = 0; t < T; ++t) rank += (L.of[t] && less(t, s)) ? 1u : 0u;
+        put(rank, s);
     }
     __syncthreads();
-    if (tid == 0) counts[dst] = kept;
+    return L.kept;
+}
+
+// The whole gate in one workgroup. Input: n = counts[src] entries (key words
+// kin[w * cin + i], amplitudes ain[i]); output: the sorted kept results at kout /
+// aout (capacity cout) and their count at counts[dst].
+__global__ __launch_bounds__(kSmallThreads) void sparse_small(const uint64_t* __restrict__ kin,
+                                                              const double2* __restrict__ ain, uint64_t cin,
+                                                              uint64_t* __restrict__ counts, int src, int dst,
+                                                              uint64_t* __restrict__ kout, double2* __restrict__ aout,
+                                                              uint64_t cout, const SparseGate g) {
+    __shared__ SmallLds L;
+    const uint64_t n64 = counts[src];
+    if (n64 > kSmallIn || n64 * (uint64_t)g.M > kSparseSmallCap) {  // the host's bound was wrong: report, change nothing
+        if (threadIdx.x == 0) counts[kErrWord] = 1;
+        return;
+    }
+    const int W = g.W;
+    const uint32_t kept = small_gate(
+        g, g.U ? g.U : g.Uin, (uint32_t)n64, L, [&](int w, uint32_t i) { return kin[w * cin + i]; },
+        [&](uint32_t i) { return ain[i]; },
+        [&](uint32_t rank, uint32_t s) {
+            for (int w = 0; w < W; ++w) kout[w * cout + rank] = L.ok[w][s];
+            aout[rank] = L.oa[s];
+        });
+    if (threadIdx.x == 0) counts[dst] = kept;
+}
+
+// A run of gates in one workgroup, the entries held in LDS from the first gate
+// to the last: the same steps as sparse_small per gate (so the same bits),
+// without a launch per gate. gl: the run's gates in device memory, matrices
+// inline. The host's bound keeps every gate of the run within the one-workgroup
+// limits; if one were not, the run stops with the error word set.
+__global__ __launch_bounds__(kSmallThreads) void sparse_small_run(const uint64_t* __restrict__ kin,
+                                                                  const double2* __restrict__ ain, uint64_t cin,
+                                                                  uint64_t* __restrict__ counts, int src, int dst,
+                                                                  uint64_t* __restrict__ kout,
+                                                                  double2* __restrict__ aout, uint64_t cout,
+                                                                  const SparseGate* __restrict__ gl, int ng) {
+    __shared__ SmallLds L;
+    __shared__ uint64_t sk[kKeyWords][kSparseSmallCap];  // the current entries
+    __shared__ double2 sa[kSparseSmallCap];
+    // The gate records, staged kRunChunk at a time with coalesced loads: read
+    // from device memory, every field a gate uses would be a dependent scalar
+    // load that misses, several per gate.
+    __shared__ __align__(16) SparseGate sg[kRunChunk];
+    const uint32_t tid = threadIdx.x;
+    const int W = gl[0].W;
+    uint64_t n64 = counts[src];
+    if (n64 > kSparseSmallCap) {
+        if (tid == 0) counts[kErrWord] = 1;
+        return;
+    }
+    uint32_t n = (uint32_t)n64;
+    for (uint32_t i = tid; i < n; i += kSmallThreads) {
+        for (int w = 0; w < W; ++w) sk[w][i] = kin[w * cin + i];
+        sa[i] = ain[i];
+    }
+    __syncthreads();
+    for (int gi = 0; gi < ng; ++gi) {
+        if (gi % kRunChunk == 0) {
+            const int c = ng - gi < kRunChunk ? ng - gi : kRunChunk;
+            const uint32_t words = (uint32_t)(c * sizeof(SparseGate) / 16);
+            const U64x2* src = reinterpret_cast<const U64x2*>(gl + gi);
+            U64x2* dst = reinterpret_cast<U64x2*>(sg);
+            for (uint32_t i = tid; i < words; i += kSmallThreads) dst[i] = src[i];
+            __syncthreads();
+        }
+        const SparseGate& g = sg[gi % kRunChunk];
+        if (n > kSmallIn || (uint64_t)n * (uint64_t)g.M > kSparseSmallCap) {
+            if (tid == 0) counts[kErrWord] = 1;
+            return;
+        }
+        n = small_gate(
+            g, g.Uin, n, L, [&](int w, uint32_t i) { return sk[w][i]; }, [&](uint32_t i) { return sa[i]; },
+            [&](uint32_t rank, uint32_t s) {
+                for (int w = 0; w < W; ++w) sk[w][rank] = L.ok[w][s];
+                sa[rank] = L.oa[s];
+            });
+    }
+    for (uint32_t i = tid; i < n; i += kSmallThreads) {
+        for (int w = 0; w < W; ++w) kout[w * cout + i] = sk[w][i];
+        aout[i] = sa[i];
+    }
+    if (tid == 0) counts[dst] = n;
 }
 
 // ---- the multi-kernel form ------------------------------------------------------
@@ -309,6 +396,36 @@ hipError_t apply_small(SparseData& d, const SparseGate& g) {
     return hipSuccess;
 }
 
+// A run of one-workgroup gates (matrices inline) in one launch.
+hipError_t apply_run(SparseData& d, const std::vector<SparseGate>& run) {
+    const size_t bytes = run.size() * sizeof(SparseGate);
+    if (d.rev_pending) {  // the previous run's records may still be on their way to the device
+        QD_TRY(hipEventSynchronize(d.rev));
+        d.rev_pending = false;
+    }
+    if (d.rhost_gates < run.size()) {
+        if (d.rhost) QD_TRY(hipHostFree(d.rhost));
+        d.rhost = nullptr;
+        d.rhost_gates = 0;
+        const size_t want = run.size() + run.size() / 2 + 16;
+        QD_TRY(hipHostMalloc(reinterpret_cast<void**>(&d.rhost), want * sizeof(SparseGate), hipHostMallocDefault));
+        d.rhost_gates = want;
+    }
+    std::memcpy(d.rhost, run.data(), bytes);
+    QD_TRY(grow(&d.rdev, &d.rdev_bytes, bytes, d.stream));
+    QD_TRY(hipMemcpyAsync(d.rdev, d.rhost, bytes, hipMemcpyHostToDevice, d.stream));
+    QD_TRY(hipEventRecord(d.rev, d.stream));
+    d.rev_pending = true;
+    const int nxt = d.cur ^ 1;
+    hipLaunchKernelGGL(sparse_small_run, dim3(1), dim3(kSmallThreads), 0, d.stream, slot_keys(d.slot[d.cur]),
+                       slot_amps(d.slot[d.cur], d.W, d.slot_cap[d.cur]), d.slot_cap[d.cur], d.nnz_dev, d.cur, nxt,
+                       slot_keys(d.slot[nxt]), slot_amps(d.slot[nxt], d.W, d.slot_cap[nxt]), d.slot_cap[nxt],
+                       static_cast<const SparseGate*>(d.rdev), (int)run.size());
+    QD_TRY(hipGetLastError());
+    d.cur = nxt;
+    return hipSuccess;
+}
+
 // n = the exact entry count (> 0). Reads the kept count back once.
 hipError_t apply_wide(SparseData& d, SparseGate g, uint32_t n) {
     const int W = d.W, M = g.M;
@@ -436,6 +553,7 @@ hipError_t sparse_init(SparseData& d, int W) {
     d.udev = static_cast<double2*>(udev);
     for (int i = 0; i < SparseData::kURing; ++i)
         if ((e = hipEventCreateWithFlags(&d.uev[i], hipEventDisableTiming)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&d.rev, hipEventDisableTiming)) != hipSuccess) return e;
     hipLaunchKernelGGL(sparse_basis, dim3(1), dim3(64), 0, d.stream, slot_keys(d.slot[0]),
                        slot_amps(d.slot[0], W, d.slot_cap[0]), W, d.slot_cap[0], d.nnz_dev);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -450,6 +568,9 @@ void sparse_release(SparseData& d) {
     for (int i = 0; i < 2; ++i)
         if (d.slot[i]) (void)hipFree(d.slot[i]);
     if (d.work) (void)hipFree(d.work);
+    if (d.rdev) (void)hipFree(d.rdev);
+    if (d.rhost) (void)hipHostFree(d.rhost);
+    if (d.rev) (void)hipEventDestroy(d.rev);
     if (d.nnz_dev) (void)hipFree(d.nnz_dev);
     for (int i = 0; i < SparseData::kURing; ++i)
         if (d.uev[i]) (void)hipEventDestroy(d.uev[i]);
@@ -509,6 +630,39 @@ hipError_t sparse_apply(SparseData& d, const SparseGate& g0, const double* U, bo
     const hipError_t er = hipEventRecord(d.uev[slot], d.stream);
     ++d.uses;
     return e != hipSuccess ? e : er;
+}
+
+hipError_t sparse_apply_list(SparseData& d, const SparseGate* gates, const double* const* U, const bool* cols_single,
+                             int count) {
+    std::vector<SparseGate> run;
+    int i = 0;
+    while (i < count) {
+        // The longest run from gate i that the bound keeps in the one-workgroup
+        // form (the test sparse_apply makes per gate), matrices inline.
+        run.clear();
+        uint64_t b = d.bound;
+        int j = i;
+        while (j < count && b != 0) {
+            const uint64_t M = (uint64_t)gates[j].M;
+            if (M > (uint64_t)kSparseInlineM || b > kSparseSmallCap / M) break;
+            SparseGate g = gates[j];
+            g.U = nullptr;
+            std::memcpy(g.Uin, U[j], M * M * sizeof(double2));
+            run.push_back(g);
+            b = cols_single[j] ? b : b * M;
+            ++j;
+        }
+        if (run.size() >= 2) {
+            QD_TRY(apply_run(d, run));
+            d.bound = b;
+            d.exact = false;
+            i = j;
+        } else {
+            QD_TRY(sparse_apply(d, gates[i], U[i], cols_single[i]));
+            ++i;
+        }
+    }
+    return hipSuccess;
 }
 
 #undef QD_TRY
