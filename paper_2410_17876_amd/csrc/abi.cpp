@@ -565,6 +565,8 @@ int sparse_gate_of(const qd_sparse* s, const int32_t* targets, int32_t k, const 
         g.tw[l] = s->word[targets[l]];
         g.ts[l] = s->stride[targets[l]];
         g.td[l] = (uint32_t)s->dims[targets[l]];
+        g.tsd[l] = qd::make_fast_div<uint64_t>(g.ts[l]);
+        g.tdd[l] = qd::make_fast_div<uint64_t>(g.td[l]);
         g.M *= s->dims[targets[l]];
     }
     if (g.M > qd::kSparseMaxM) return set_err(QD_ERR_NOT_SUPPORTED, "sparse gates act on at most 16 amplitudes");
@@ -575,6 +577,8 @@ int sparse_gate_of(const qd_sparse* s, const int32_t* targets, int32_t k, const 
         g.cw[l] = s->word[controls[l]];
         g.cs[l] = s->stride[controls[l]];
         g.cd[l] = (uint32_t)s->dims[controls[l]];
+        g.csd[l] = qd::make_fast_div<uint64_t>(g.cs[l]);
+        g.cdd[l] = qd::make_fast_div<uint64_t>(g.cd[l]);
         g.cv[l] = (uint32_t)values[l];
     }
     for (int a = 0; a < g.M; ++a) {

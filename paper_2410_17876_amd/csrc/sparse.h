@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "plan.h"
 #include "qd.h"
 
 namespace qd {
@@ -49,6 +50,10 @@ struct SparseGate {
     uint32_t cd[QD_MAX_CONTROLS];
     uint32_t cv[QD_MAX_CONTROLS];
     int M;                                // class size
+    // digit of a target / control: (word / stride) mod dim, both divisions by
+    // multiply-high (64-bit divisions are long instruction sequences on the GPU)
+    FastDiv<uint64_t> tsd[QD_MAX_TARGETS], tdd[QD_MAX_TARGETS];
+    FastDiv<uint64_t> csd[QD_MAX_CONTROLS], cdd[QD_MAX_CONTROLS];
     uint64_t off[kSparseMaxM][kKeyWords]; // member a sits at class base + off[a] (word by word)
     const double2* U;                     // M x M row-major [out][in], device-readable; null: Uin holds it
     double2 Uin[kSparseInlineM * kSparseInlineM];  // U itself when M <= kSparseInlineM (one-workgroup form)

@@ -36,22 +36,26 @@ namespace qd {
 namespace {
 
 constexpr int kSmallThreads = 512;
-constexpr int kRunChunk = 24;  // gate records a run keeps in LDS at a time
+constexpr int kRunChunk = 16;  // gate records a run keeps in LDS at a time
 typedef unsigned long long U64x2 __attribute__((ext_vector_type(2)));
 static_assert(sizeof(SparseGate) % 16 == 0, "gate records are copied in 16-byte pieces");
 constexpr uint32_t kSmallIn = kSparseSmallCap / 2;  // entries of a small gate (class size >= 2)
 constexpr int kErrWord = 2;                         // nnz_dev[2]: set if a small gate saw more entries than planned
 
-__device__ __forceinline__ uint32_t digit_of(uint64_t v, uint64_t s, uint32_t d) { return (uint32_t)((v / s) % d); }
+__device__ __forceinline__ uint32_t digit_of(uint64_t v, const FastDiv<uint64_t>& s, const FastDiv<uint64_t>& dd,
+                                             uint32_t d) {
+    const uint64_t q = fast_div<uint64_t>(v, s);
+    return (uint32_t)(q - fast_div<uint64_t>(q, dd) * (uint64_t)d);
+}
 
 // Group of one entry: returns its local index (the key becomes the class base)
 // when every control holds, else -1 (the key is left as it is).
 __device__ __forceinline__ int classify(const SparseGate& g, uint64_t (&key)[kKeyWords]) {
     for (int l = 0; l < g.m; ++l)
-        if (digit_of(key[g.cw[l]], g.cs[l], g.cd[l]) != g.cv[l]) return -1;
+        if (digit_of(key[g.cw[l]], g.csd[l], g.cdd[l], g.cd[l]) != g.cv[l]) return -1;
     int a = 0, w = 1;
     for (int l = 0; l < g.k; ++l) {
-        const uint32_t dg = digit_of(key[g.tw[l]], g.ts[l], g.td[l]);
+        const uint32_t dg = digit_of(key[g.tw[l]], g.tsd[l], g.tdd[l], g.td[l]);
         a += (int)dg * w;
         w *= (int)g.td[l];
         key[g.tw[l]] -= (uint64_t)dg * g.ts[l];
@@ -62,18 +66,27 @@ __device__ __forceinline__ int classify(const SparseGate& g, uint64_t (&key)[kKe
 // Row r of U x over the present members of a class (bit a of `present`), in
 // ascending a, as textbook complex products with no FMA contraction: which
 // results are exactly zero (and dropped) then does not depend on how the
-// compiler would fuse them.
+// compiler would fuse them. The loop runs over compile-time indices, so x stays
+// in registers (a runtime index would put it in scratch memory).
 __device__ __forceinline__ double2 class_row(const double2* U, const double2 (&x)[kSparseMaxM], uint32_t present,
                                              int r, int M) {
 #pragma clang fp contract(off)
     double yr = 0.0, yi = 0.0;
-    for (int a = 0; a < M; ++a) {
-        if (!((present >> a) & 1u)) continue;
+#pragma unroll
+    for (int a = 0; a < kSparseMaxM; ++a) {
+        if (a >= M || !((present >> a) & 1u)) continue;
         const double2 u = U[r * M + a];
         yr = yr + (u.x * x[a].x - u.y * x[a].y);
         yi = yi + (u.x * x[a].y + u.y * x[a].x);
     }
     return double2{yr, yi};
+}
+
+// x[la] = v with compile-time indices only (see class_row).
+__device__ __forceinline__ void set_member(double2 (&x)[kSparseMaxM], int la, double2 v) {
+#pragma unroll
+    for (int a = 0; a < kSparseMaxM; ++a)
+        if (a == la) x[a] = v;
 }
 
 // LDS of the one-workgroup form: the gate's grouping and its results.
@@ -113,7 +126,9 @@ __device__ __forceinline__ uint32_t small_gate(const SparseGate& g, const double
     for (uint32_t i = tid; i < (uint32_t)(M * M); i += kSmallThreads) L.su[i] = U[i];
     for (uint32_t i = tid; i < n; i += kSmallThreads) {
         uint64_t key[kKeyWords] = {0, 0, 0};
-        for (int w = 0; w < W; ++w) key[w] = kin(w, i);
+#pragma unroll
+        for (int w = 0; w < kKeyWords; ++w)
+            if (w < W) key[w] = kin(w, i);
         L.la[i] = classify(g, key);
         for (int w = 0; w < kKeyWords; ++w) L.gk[w][i] = key[w];
     }
@@ -140,7 +155,7 @@ __device__ __forceinline__ uint32_t small_gate(const SparseGate& g, const double
         uint32_t present = 0;
         for (uint32_t j = i; j < n; ++j)
             if (same(i, j)) {
-                x[L.la[j]] = ain(j);
+                set_member(x, L.la[j], ain(j));
                 present |= 1u << L.la[j];
             }
         for (int r = 0; r < M; ++r) {
@@ -299,7 +314,7 @@ __global__ void wide_classes(const uint64_t* __restrict__ sg, const uint32_t* __
     uint32_t present = 0;
     for (uint32_t j = i; j < n && same(i, j); ++j) {
         const uint32_t e = sidx[j];
-        x[la[e]] = ain[e];
+        set_member(x, la[e], ain[e]);
         present |= 1u << la[e];
     }
     for (int r = 0; r < M; ++r) {
