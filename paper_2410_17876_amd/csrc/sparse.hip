@@ -243,7 +243,17 @@ __global__ __launch_bounds__(kSmallThreads) void sparse_small_run(const uint64_t
             const uint32_t words = (uint32_t)(c * sizeof(SparseGate) / 16);
             const U64x2* src = reinterpret_cast<const U64x2*>(gl + gi);
             U64x2* dst = reinterpret_cast<U64x2*>(sg);
-            for (uint32_t i = tid; i < words; i += kSmallThreads) dst[i] = src[i];
+            // kStage loads in flight per thread before the first store.
+            constexpr int kStage = 8;
+            for (uint32_t i0 = tid; i0 < words; i0 += kSmallThreads * kStage) {
+                U64x2 v[kStage];
+#pragma unroll
+                for (int u = 0; u < kStage; ++u)
+                    if (i0 + u * kSmallThreads < words) v[u] = src[i0 + u * kSmallThreads];
+#pragma unroll
+                for (int u = 0; u < kStage; ++u)
+                    if (i0 + u * kSmallThreads < words) dst[i0 + u * kSmallThreads] = v[u];
+            }
             __syncthreads();
         }
         const SparseGate& g = sg[gi % kRunChunk];
