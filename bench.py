@@ -302,10 +302,12 @@ def run_batched(qd, precision, steps, warmup, tune_cache, lookahead):
     runner = qd.batch.BatchRunner([s.dims for s in specs], precision)
     ab = 16 if precision == "c128" else 8
     updates = 0
+    flops = 0
     pass_bytes = 0
     for s, gl in zip(specs, lists):
         infos = [qd.gate_info(s.dims, g.targets, g.U, g.controls, g.values, precision) for g in gl.gates]
         updates += sum(i["updated"] for i in infos)
+        flops += sum(i["flops"] for i in infos)
         npass = len(qd.circuit_plan(s.dims, gl, precision, tile_amps=tile, min_run=run_len, reorder=lookahead))
         pass_bytes += npass * 2 * s.D * ab
     t0 = time.time()
@@ -330,6 +332,7 @@ def run_batched(qd, precision, steps, warmup, tune_cache, lookahead):
     torch.cuda.empty_cache()
     log(f"batched {precision}: norms of the first states {norms[:3]}")
     achieved = pass_bytes * steps / wall / 1e9
+    alu = flops * steps / wall / 1e12
     return {"value": updates * steps / wall, "unit": "updates/s", "dtype": "f64" if precision == "c128" else "f32",
             "ms_per_step": 1e3 * wall / steps, "ms_per_step_eager_launches": 1e3 * timing["eager"] / steps,
             "launch_rounds_per_step": rounds, "items_per_step": items,
@@ -338,7 +341,12 @@ def run_batched(qd, precision, steps, warmup, tune_cache, lookahead):
             "autotuned": {"tile_amps": tile, "min_run": run_len, "timings_s": tuned.get("timings_s")},
             "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                          "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": None, "kernel": "batch_tile",
-                         "note": "whole-run average over all rounds: 2 x D x bytes per (state, pass)"}}
+                         # the same run against the vector ALU: the gates' useful flops
+                         # (8 M per changed amplitude, dense gates) over the FP64 / FP32 vector peak
+                         "alu_tflops": round(alu, 2), "alu_peak_tflops": PEAK_VALU_TFLOPS[precision],
+                         "alu_frac": round(alu / PEAK_VALU_TFLOPS[precision], 4),
+                         "note": "whole-run averages over all rounds: 2 x D x bytes per (state, pass); "
+                                 "the gates' useful flops"}}
 
 
 def run_served(qd, n_closed, n_open, loads, lookahead):
