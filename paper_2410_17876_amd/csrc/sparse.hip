@@ -166,16 +166,32 @@ __device__ __forceinline__ uint32_t small_gate(const SparseGate& g, const double
         }
     }
     __syncthreads();
-    uint32_t mine = 0;
-    for (uint32_t s = tid; s < T; s += kSmallThreads) mine += L.of[s];
-    if (mine) atomicAdd(&L.kept, mine);
     // Each kept result goes to its rank among the kept keys (keys are distinct:
     // classes are disjoint and control-failing keys meet no class).
-    for (uint32_t s = tid; s < T; s += kSmallThreads) {
-        if (!L.of[s]) continue;
-        uint32_t rank = 0;
-        for (uint32_t t = 0; t < T; ++t) rank += (L.of[t] && less(t, s)) ? 1u : 0u;
-        put(rank, s);
+    if (T <= 64) {
+        // One wavefront: a ballot of the flags gives the kept slots, and each kept
+        // result compares itself with those only, not with all T slots.
+        if (tid < 64) {
+            const bool k = tid < T && L.of[tid];
+            const uint64_t kept = __ballot(k);
+            if (tid == 0) L.kept = (uint32_t)__popcll(kept);
+            if (k) {
+                uint32_t rank = 0;
+                for (uint64_t m = kept; m; m &= m - 1)
+                    rank += less((uint32_t)__builtin_ctzll(m), tid) ? 1u : 0u;
+                put(rank, tid);
+            }
+        }
+    } else {
+        uint32_t mine = 0;
+        for (uint32_t s = tid; s < T; s += kSmallThreads) mine += L.of[s];
+        if (mine) atomicAdd(&L.kept, mine);
+        for (uint32_t s = tid; s < T; s += kSmallThreads) {
+            if (!L.of[s]) continue;
+            uint32_t rank = 0;
+            for (uint32_t t = 0; t < T; ++t) rank += (L.of[t] && less(t, s)) ? 1u : 0u;
+            put(rank, s);
+        }
     }
     __syncthreads();
     return L.kept;
