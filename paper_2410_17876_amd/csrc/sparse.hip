@@ -104,7 +104,7 @@ struct SmallLds {
 // workgroup: key word w of entry i is kin(w, i), its amplitude ain(i); the kept
 // results are handed, in key order, to put(rank, s) (output slot s of L). Entry
 // i's results take output slots i * M .. i * M + M - 1 (only a group's first
-// entry fills them). Returns the kept count (after a barrier; uniform). The
+// entry's slots are filled, one thread per slot). Returns the kept count (after a barrier; uniform). The
 // inputs are last read before the second barrier and put runs after it, so put
 // may overwrite them.
 template <typename KIn, typename AIn, typename Put>
@@ -135,7 +135,10 @@ __device__ __forceinline__ uint32_t small_gate(const SparseGate& g, const double
     for (uint32_t s = tid; s < T; s += kSmallThreads) L.of[s] = 0;
     if (tid == 0) L.kept = 0;
     __syncthreads();
-    for (uint32_t i = tid; i < n; i += kSmallThreads) {
+    // One thread per output slot s = i * M + r: if entry i leads its group, row r
+    // of U times the group's members.
+    for (uint32_t s = tid; s < T; s += kSmallThreads) {
+        const uint32_t i = s / (uint32_t)M, r = s - i * (uint32_t)M;
         bool lead = true;
         for (uint32_t j = 0; j < i; ++j)
             if (same(i, j)) {
@@ -143,11 +146,12 @@ __device__ __forceinline__ uint32_t small_gate(const SparseGate& g, const double
                 break;
             }
         if (!lead) continue;
-        const uint32_t o = i * (uint32_t)M;
-        if (L.la[i] < 0) {  // controls fail: unchanged
-            for (int w = 0; w < kKeyWords; ++w) L.ok[w][o] = L.gk[w][i];
-            L.oa[o] = ain(i);
-            L.of[o] = 1;
+        if (L.la[i] < 0) {  // controls fail: unchanged, in the group's first slot
+            if (r == 0) {
+                for (int w = 0; w < kKeyWords; ++w) L.ok[w][s] = L.gk[w][i];
+                L.oa[s] = ain(i);
+                L.of[s] = 1;
+            }
             continue;
         }
         double2 x[kSparseMaxM];
@@ -158,12 +162,10 @@ __device__ __forceinline__ uint32_t small_gate(const SparseGate& g, const double
                 set_member(x, L.la[j], ain(j));
                 present |= 1u << L.la[j];
             }
-        for (int r = 0; r < M; ++r) {
-            const double2 y = class_row(L.su, x, present, r, M);
-            for (int w = 0; w < kKeyWords; ++w) L.ok[w][o + r] = L.gk[w][i] + g.off[r][w];
-            L.oa[o + r] = y;
-            L.of[o + r] = (y.x != 0.0 || y.y != 0.0) ? 1 : 0;
-        }
+        const double2 y = class_row(L.su, x, present, (int)r, M);
+        for (int w = 0; w < kKeyWords; ++w) L.ok[w][s] = L.gk[w][i] + g.off[r][w];
+        L.oa[s] = y;
+        L.of[s] = (y.x != 0.0 || y.y != 0.0) ? 1 : 0;
     }
     __syncthreads();
     // Each kept result goes to its rank among the kept keys (keys are distinct:
