@@ -68,12 +68,12 @@ __device__ __forceinline__ int classify(const SparseGate& g, uint64_t (&key)[kKe
 // results are exactly zero (and dropped) then does not depend on how the
 // compiler would fuse them. The loop runs over compile-time indices, so x stays
 // in registers (a runtime index would put it in scratch memory).
-__device__ __forceinline__ double2 class_row(const double2* U, const double2 (&x)[kSparseMaxM], uint32_t present,
-                                             int r, int M) {
+template <int N>
+__device__ __forceinline__ double2 class_row(const double2* U, const double2 (&x)[N], uint32_t present, int r, int M) {
 #pragma clang fp contract(off)
     double yr = 0.0, yi = 0.0;
 #pragma unroll
-    for (int a = 0; a < kSparseMaxM; ++a) {
+    for (int a = 0; a < N; ++a) {
         if (a >= M || !((present >> a) & 1u)) continue;
         const double2 u = U[r * M + a];
         yr = yr + (u.x * x[a].x - u.y * x[a].y);
@@ -83,9 +83,10 @@ __device__ __forceinline__ double2 class_row(const double2* U, const double2 (&x
 }
 
 // x[la] = v with compile-time indices only (see class_row).
-__device__ __forceinline__ void set_member(double2 (&x)[kSparseMaxM], int la, double2 v) {
+template <int N>
+__device__ __forceinline__ void set_member(double2 (&x)[N], int la, double2 v) {
 #pragma unroll
-    for (int a = 0; a < kSparseMaxM; ++a)
+    for (int a = 0; a < N; ++a)
         if (a == la) x[a] = v;
 }
 
@@ -100,14 +101,14 @@ struct SmallLds {
     uint32_t kept;
 };
 
-// One gate on n <= kSmallIn entries (n * M <= kSparseSmallCap), the whole
-// workgroup: key word w of entry i is kin(w, i), its amplitude ain(i); the kept
-// results are handed, in key order, to put(rank, s) (output slot s of L). Entry
-// i's results take output slots i * M .. i * M + M - 1 (only a group's first
-// entry's slots are filled, one thread per slot). Returns the kept count (after a barrier; uniform). The
-// inputs are last read before the second barrier and put runs after it, so put
-// may overwrite them.
-template <typename KIn, typename AIn, typename Put>
+// One gate on n <= kSmallIn entries (n * M <= kSparseSmallCap, M <= MaxM), the
+// whole workgroup: key word w of entry i is kin(w, i), its amplitude ain(i); the
+// kept results are handed, in key order, to put(rank, s) (output slot s of L).
+// Entry i's results take output slots i * M .. i * M + M - 1 (only a group's
+// first entry's slots are filled, one thread per slot). Returns the kept count
+// (after a barrier; uniform). The inputs are last read before the second barrier
+// and put runs after it, so put may overwrite them.
+template <int MaxM, typename KIn, typename AIn, typename Put>
 __device__ __forceinline__ uint32_t small_gate(const SparseGate& g, const double2* U, uint32_t n, SmallLds& L,
                                                const KIn& kin, const AIn& ain, const Put& put) {
     const uint32_t tid = threadIdx.x;
@@ -154,8 +155,9 @@ __device__ __forceinline__ uint32_t small_gate(const SparseGate& g, const double
             }
             continue;
         }
-        double2 x[kSparseMaxM];
-        for (int a = 0; a < kSparseMaxM; ++a) x[a] = double2{0.0, 0.0};
+        double2 x[MaxM];
+#pragma unroll
+        for (int a = 0; a < MaxM; ++a) x[a] = double2{0.0, 0.0};
         uint32_t present = 0;
         for (uint32_t j = i; j < n; ++j)
             if (same(i, j)) {
@@ -214,7 +216,7 @@ __global__ __launch_bounds__(kSmallThreads) void sparse_small(const uint64_t* __
         return;
     }
     const int W = g.W;
-    const uint32_t kept = small_gate(
+    const uint32_t kept = small_gate<kSparseMaxM>(
         g, g.U ? g.U : g.Uin, (uint32_t)n64, L, [&](int w, uint32_t i) { return kin[w * cin + i]; },
         [&](uint32_t i) { return ain[i]; },
         [&](uint32_t rank, uint32_t s) {
@@ -275,11 +277,11 @@ __global__ __launch_bounds__(kSmallThreads) void sparse_small_run(const uint64_t
             __syncthreads();
         }
         const SparseGate& g = sg[gi % kRunChunk];
-        if (n > kSmallIn || (uint64_t)n * (uint64_t)g.M > kSparseSmallCap) {
+        if (n > kSmallIn || g.M > kSparseInlineM || (uint64_t)n * (uint64_t)g.M > kSparseSmallCap) {
             if (tid == 0) counts[kErrWord] = 1;
             return;
         }
-        n = small_gate(
+        n = small_gate<kSparseInlineM>(
             g, g.Uin, n, L, [&](int w, uint32_t i) { return sk[w][i]; }, [&](uint32_t i) { return sa[i]; },
             [&](uint32_t rank, uint32_t s) {
                 for (int w = 0; w < W; ++w) sk[w][rank] = L.ok[w][s];
