@@ -107,12 +107,13 @@ struct SmallLds {
 // Entry i's results take output slots i * M .. i * M + M - 1 (only a group's
 // first entry's slots are filled, one thread per slot). Returns the kept count
 // (after a barrier; uniform). The inputs are last read before the second barrier
-// and put runs after it, so put may overwrite them.
-template <int MaxM, typename KIn, typename AIn, typename Put>
+// and put runs after it, so put may overwrite them. W: the key words (g.W). U:
+// the matrix, copied to LDS first unless ULds (U already in LDS).
+template <int MaxM, int W, bool ULds, typename KIn, typename AIn, typename Put>
 __device__ __forceinline__ uint32_t small_gate(const SparseGate& g, const double2* U, uint32_t n, SmallLds& L,
                                                const KIn& kin, const AIn& ain, const Put& put) {
     const uint32_t tid = threadIdx.x;
-    const int W = g.W, M = g.M;
+    const int M = g.M;
     const uint32_t T = n * (uint32_t)M;
     auto same = [&](uint32_t i, uint32_t j) {
         for (int w = 0; w < W; ++w)
@@ -124,14 +125,16 @@ __device__ __forceinline__ uint32_t small_gate(const SparseGate& g, const double
             if (L.ok[w][s] != L.ok[w][t]) return L.ok[w][s] < L.ok[w][t];
         return false;
     };
-    for (uint32_t i = tid; i < (uint32_t)(M * M); i += kSmallThreads) L.su[i] = U[i];
+    if (!ULds)
+        for (uint32_t i = tid; i < (uint32_t)(M * M); i += kSmallThreads) L.su[i] = U[i];
+    const double2* Ur = ULds ? U : L.su;
     for (uint32_t i = tid; i < n; i += kSmallThreads) {
         uint64_t key[kKeyWords] = {0, 0, 0};
 #pragma unroll
-        for (int w = 0; w < kKeyWords; ++w)
-            if (w < W) key[w] = kin(w, i);
+        for (int w = 0; w < W; ++w) key[w] = kin(w, i);
         L.la[i] = classify(g, key);
-        for (int w = 0; w < kKeyWords; ++w) L.gk[w][i] = key[w];
+#pragma unroll
+        for (int w = 0; w < W; ++w) L.gk[w][i] = key[w];
     }
     for (uint32_t s = tid; s < T; s += kSmallThreads) L.of[s] = 0;
     if (tid == 0) L.kept = 0;
@@ -149,7 +152,8 @@ __device__ __forceinline__ uint32_t small_gate(const SparseGate& g, const double
         if (!lead) continue;
         if (L.la[i] < 0) {  // controls fail: unchanged, in the group's first slot
             if (r == 0) {
-                for (int w = 0; w < kKeyWords; ++w) L.ok[w][s] = L.gk[w][i];
+#pragma unroll
+                for (int w = 0; w < W; ++w) L.ok[w][s] = L.gk[w][i];
                 L.oa[s] = ain(i);
                 L.of[s] = 1;
             }
@@ -164,8 +168,9 @@ __device__ __forceinline__ uint32_t small_gate(const SparseGate& g, const double
                 set_member(x, L.la[j], ain(j));
                 present |= 1u << L.la[j];
             }
-        const double2 y = class_row(L.su, x, present, (int)r, M);
-        for (int w = 0; w < kKeyWords; ++w) L.ok[w][s] = L.gk[w][i] + g.off[r][w];
+        const double2 y = class_row(Ur, x, present, (int)r, M);
+#pragma unroll
+        for (int w = 0; w < W; ++w) L.ok[w][s] = L.gk[w][i] + g.off[r][w];
         L.oa[s] = y;
         L.of[s] = (y.x != 0.0 || y.y != 0.0) ? 1 : 0;
     }
@@ -203,7 +208,8 @@ __device__ __forceinline__ uint32_t small_gate(const SparseGate& g, const double
 
 // The whole gate in one workgroup. Input: n = counts[src] entries (key words
 // kin[w * cin + i], amplitudes ain[i]); output: the sorted kept results at kout /
-// aout (capacity cout) and their count at counts[dst].
+// aout (capacity cout) and their count at counts[dst]. W: the state's key words.
+template <int W>
 __global__ __launch_bounds__(kSmallThreads) void sparse_small(const uint64_t* __restrict__ kin,
                                                               const double2* __restrict__ ain, uint64_t cin,
                                                               uint64_t* __restrict__ counts, int src, int dst,
@@ -211,12 +217,11 @@ __global__ __launch_bounds__(kSmallThreads) void sparse_small(const uint64_t* __
                                                               uint64_t cout, const SparseGate g) {
     __shared__ SmallLds L;
     const uint64_t n64 = counts[src];
-    if (n64 > kSmallIn || n64 * (uint64_t)g.M > kSparseSmallCap) {  // the host's bound was wrong: report, change nothing
+    if (n64 > kSmallIn || n64 * (uint64_t)g.M > kSparseSmallCap || g.W != W) {  // the host's bound was wrong: report, change nothing
         if (threadIdx.x == 0) counts[kErrWord] = 1;
         return;
     }
-    const int W = g.W;
-    const uint32_t kept = small_gate<kSparseMaxM>(
+    const uint32_t kept = small_gate<kSparseMaxM, W, false>(
         g, g.U ? g.U : g.Uin, (uint32_t)n64, L, [&](int w, uint32_t i) { return kin[w * cin + i]; },
         [&](uint32_t i) { return ain[i]; },
         [&](uint32_t rank, uint32_t s) {
@@ -230,7 +235,9 @@ __global__ __launch_bounds__(kSmallThreads) void sparse_small(const uint64_t* __
 // to the last: the same steps as sparse_small per gate (so the same bits),
 // without a launch per gate. gl: the run's gates in device memory, matrices
 // inline. The host's bound keeps every gate of the run within the one-workgroup
-// limits; if one were not, the run stops with the error word set.
+// limits; if one were not, the run stops with the error word set. W: the state's
+// key words.
+template <int W>
 __global__ __launch_bounds__(kSmallThreads) void sparse_small_run(const uint64_t* __restrict__ kin,
                                                                   const double2* __restrict__ ain, uint64_t cin,
                                                                   uint64_t* __restrict__ counts, int src, int dst,
@@ -245,7 +252,6 @@ __global__ __launch_bounds__(kSmallThreads) void sparse_small_run(const uint64_t
     // load that misses, several per gate.
     __shared__ __align__(16) SparseGate sg[kRunChunk];
     const uint32_t tid = threadIdx.x;
-    const int W = gl[0].W;
     uint64_t n64 = counts[src];
     if (n64 > kSparseSmallCap) {
         if (tid == 0) counts[kErrWord] = 1;
@@ -277,11 +283,11 @@ __global__ __launch_bounds__(kSmallThreads) void sparse_small_run(const uint64_t
             __syncthreads();
         }
         const SparseGate& g = sg[gi % kRunChunk];
-        if (n > kSmallIn || g.M > kSparseInlineM || (uint64_t)n * (uint64_t)g.M > kSparseSmallCap) {
+        if (n > kSmallIn || g.M > kSparseInlineM || g.W != W || (uint64_t)n * (uint64_t)g.M > kSparseSmallCap) {
             if (tid == 0) counts[kErrWord] = 1;
             return;
         }
-        n = small_gate<kSparseInlineM>(
+        n = small_gate<kSparseInlineM, W, true>(
             g, g.Uin, n, L, [&](int w, uint32_t i) { return sk[w][i]; }, [&](uint32_t i) { return sa[i]; },
             [&](uint32_t rank, uint32_t s) {
                 for (int w = 0; w < W; ++w) sk[w][rank] = L.ok[w][s];
@@ -433,7 +439,8 @@ hipError_t grow_slot(SparseData& d, int i, uint64_t entries) {
 
 hipError_t apply_small(SparseData& d, const SparseGate& g) {
     const int nxt = d.cur ^ 1;
-    hipLaunchKernelGGL(sparse_small, dim3(1), dim3(kSmallThreads), 0, d.stream, slot_keys(d.slot[d.cur]),
+    hipLaunchKernelGGL(d.W == 1 ? sparse_small<1> : d.W == 2 ? sparse_small<2> : sparse_small<3>, dim3(1),
+                       dim3(kSmallThreads), 0, d.stream, slot_keys(d.slot[d.cur]),
                        slot_amps(d.slot[d.cur], d.W, d.slot_cap[d.cur]), d.slot_cap[d.cur], d.nnz_dev, d.cur, nxt,
                        slot_keys(d.slot[nxt]), slot_amps(d.slot[nxt], d.W, d.slot_cap[nxt]), d.slot_cap[nxt], g);
     QD_TRY(hipGetLastError());
@@ -462,7 +469,8 @@ hipError_t apply_run(SparseData& d, const std::vector<SparseGate>& run) {
     QD_TRY(hipEventRecord(d.rev, d.stream));
     d.rev_pending = true;
     const int nxt = d.cur ^ 1;
-    hipLaunchKernelGGL(sparse_small_run, dim3(1), dim3(kSmallThreads), 0, d.stream, slot_keys(d.slot[d.cur]),
+    hipLaunchKernelGGL(d.W == 1 ? sparse_small_run<1> : d.W == 2 ? sparse_small_run<2> : sparse_small_run<3>,
+                       dim3(1), dim3(kSmallThreads), 0, d.stream, slot_keys(d.slot[d.cur]),
                        slot_amps(d.slot[d.cur], d.W, d.slot_cap[d.cur]), d.slot_cap[d.cur], d.nnz_dev, d.cur, nxt,
                        slot_keys(d.slot[nxt]), slot_amps(d.slot[nxt], d.W, d.slot_cap[nxt]), d.slot_cap[nxt],
                        static_cast<const SparseGate*>(d.rdev), (int)run.size());
