@@ -36,7 +36,8 @@ namespace qd {
 namespace {
 
 constexpr int kSmallThreads = 512;
-constexpr int kRunChunk = 16;  // gate records a run keeps in LDS at a time
+constexpr int kRunChunk = 16;         // gate records a run keeps in LDS at a time
+constexpr size_t kRunInitGates = 256;  // gate records a new state can stage for runs
 typedef unsigned long long U64x2 __attribute__((ext_vector_type(2)));
 static_assert(sizeof(SparseGate) % 16 == 0, "gate records are copied in 16-byte pieces");
 constexpr uint32_t kSmallIn = kSparseSmallCap / 2;  // entries of a small gate (class size >= 2)
@@ -607,6 +608,15 @@ hipError_t sparse_init(SparseData& d, int W) {
     for (int i = 0; i < SparseData::kURing; ++i)
         if ((e = hipEventCreateWithFlags(&d.uev[i], hipEventDisableTiming)) != hipSuccess) return e;
     if ((e = hipEventCreateWithFlags(&d.rev, hipEventDisableTiming)) != hipSuccess) return e;
+    // Staging for the gate records of runs, sized for kRunInitGates (longer
+    // lists grow it), so that a new state's first gate list allocates nothing.
+    if ((e = hipHostMalloc(reinterpret_cast<void**>(&d.rhost), kRunInitGates * sizeof(SparseGate),
+                           hipHostMallocDefault)) != hipSuccess) {
+        d.rhost = nullptr;
+        return e;
+    }
+    d.rhost_gates = kRunInitGates;
+    if ((e = grow(&d.rdev, &d.rdev_bytes, kRunInitGates * sizeof(SparseGate), d.stream)) != hipSuccess) return e;
     hipLaunchKernelGGL(sparse_basis, dim3(1), dim3(64), 0, d.stream, slot_keys(d.slot[0]),
                        slot_amps(d.slot[0], W, d.slot_cap[0]), W, d.slot_cap[0], d.nnz_dev);
     if ((e = hipGetLastError()) != hipSuccess) return e;
